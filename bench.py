@@ -1,0 +1,227 @@
+"""Throughput of the fused collide-and-stream step on one MI355X.
+
+Headline: D3Q107, 256^3 periodic grid, smooth seeded perturbation (amplitude
+0.01 in rho and T, 0.02 in u), gamma 1.4 (delta 2), tau_f = tau_g = 0.65,
+populations in FP32 deviation storage, 500 timed steps.  The other three
+paths (D3Q107 FP64; D2Q37 4096^2 FP32 and FP64 with tau_f 0.7, tau_g 0.8)
+are measured the same way and reported under "paths".
+
+One step = one launch of the fused step kernel over the whole grid (pull,
+moments, equilibrium, BGK relaxation of g and h, store).  Inputs are resident
+in HBM before the timed region; the timed region holds exactly K steps
+bracketed by device synchronisation, timed with HIP events recorded on the
+stream the kernels run on.
+
+Roofline: algorithmic bytes per cell update = 2 (read + write) x Q x 2
+(g and h) x bytes per value; achieved GB/s = those bytes x cells / average
+launch time; peak = 8 TB/s HBM3E.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+PATHS = {
+    "d3q107_fp32": dict(dim=3, shape=(256, 256, 256), gamma=1.4, tf=0.65, tg=0.65, fp32=True,
+                        seed=3, steps=500),
+    "d3q107_fp64": dict(dim=3, shape=(256, 256, 256), gamma=1.4, tf=0.65, tg=0.65, fp32=False,
+                        seed=3, steps=500),
+    "d2q37_fp32": dict(dim=2, shape=(4096, 4096, 1), gamma=1.4, tf=0.7, tg=0.8, fp32=True,
+                       seed=2, steps=1000),
+    "d2q37_fp64": dict(dim=2, shape=(4096, 4096, 1), gamma=1.4, tf=0.7, tg=0.8, fp32=False,
+                       seed=2, steps=1000),
+}
+
+
+def bytes_per_update(dim, fp32):
+    q = 37 if dim == 2 else 107
+    return 2 * q * 2 * (4 if fp32 else 8)
+
+
+def describe(name, p):
+    q = 37 if p["dim"] == 2 else 107
+    grid = "x".join(str(n) for n in p["shape"][:p["dim"]])
+    delta = 2.0 / (p["gamma"] - 1.0) - p["dim"]
+    return (f"D{p['dim']}Q{q} {grid} periodic, smooth seeded field (seed {p['seed']}), "
+            f"gamma {p['gamma']} (delta {delta:g}), tau_f {p['tf']}, tau_g {p['tg']}, "
+            f"{'FP32 deviation storage' if p['fp32'] else 'FP64'}")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "velocity_set.h", "lbm_internal.h"):
+        with open(os.path.join(ROOT, "paper_1608_06345_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name, cells):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    ent = rec.get(name)
+    if not ent or ent.get("kernel_hash") != kernel_source_hash():
+        return None
+    if ent.get("cells") != cells:
+        return None
+    return ent["bytes_per_launch"]
+
+
+def run_path(name, p, steps, warmup):
+    import torch
+
+    from paper_1608_06345_amd import lbm
+    from paper_1608_06345_amd.inputs import smooth_fields
+
+    nx, ny, nz = p["shape"]
+    cells = nx * ny * nz
+    prec = lbm.LBM_FP32_DEV if p["fp32"] else lbm.LBM_FP64
+    f = smooth_fields(p["dim"], nx, ny, nz, seed=p["seed"])
+    stream = torch.cuda.current_stream()
+    with lbm.Solver(p["dim"], p["gamma"], p["tf"], p["tg"], nx, ny, nz, precision=prec) as s:
+        s.set_stream(stream)
+        dev = [torch.from_numpy(a.reshape(-1)).to("cuda") for a in f]
+        lbm.lbm_init_fields_dev(s.h, *dev)
+        s.step(warmup)
+        torch.cuda.synchronize()
+        del dev
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(stream)
+        s.step(steps)
+        end.record(stream)
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(end)
+        mass, mom, energy = s.totals()
+    ms_step = ms / steps
+    mlups = cells * steps / (ms * 1e-3) / 1e6
+    bpu = bytes_per_update(p["dim"], p["fp32"])
+    achieved = bpu * cells / (ms_step * 1e-3) / 1e9
+    traffic = measured_traffic(name, cells)
+    return {
+        "workload": describe(name, p), "cells": cells, "steps": steps,
+        "ms_per_step": round(ms_step, 4), "mlups": round(mlups, 1),
+        "gbs": round(achieved, 1), "hbm_frac": round(achieved / PEAK_HBM_GBS, 4),
+        "bytes_per_update": bpu, "traffic_bytes_per_launch": traffic,
+        "mass": mass, "energy": energy,
+    }
+
+
+def cpu_baseline(p, seconds_hint=15.0):
+    """The FP64 oracle, as it stands, on a bounded sample of the headline
+    workload: the same lattice, parameters and field recipe on a 64^3 grid
+    (256^3 would take over a minute per step on the host), timed over a
+    fixed number of steps.  MLUPS is per cell update, so it needs no
+    rescaling.  The GPU runs the same sample; its deviation from the oracle
+    is reported alongside."""
+    import numpy as np
+
+    from oracle.model import OracleLBM, num_threads
+    from paper_1608_06345_amd import lbm
+    from paper_1608_06345_amd.inputs import smooth_fields
+
+    n = 64
+    dim = p["dim"]
+    shape = (n, n, n) if dim == 3 else (4 * n, 4 * n, 1)
+    steps = 50
+    f = smooth_fields(dim, *shape, seed=p["seed"])
+    o = OracleLBM(dim, p["gamma"], p["tf"], p["tg"], *shape)
+    o.init_fields(*f)
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    cells = shape[0] * shape[1] * shape[2]
+    r_o, u_o, E_o = o.moments()
+    T_o = o.temperature(u_o, E_o)
+    prec = lbm.LBM_FP32_DEV if p["fp32"] else lbm.LBM_FP64
+    with lbm.Solver(dim, p["gamma"], p["tf"], p["tg"], *shape, precision=prec) as s:
+        s.init_fields(*f)
+        s.step(steps)
+        r, u, E = s.moments()
+        T = s.temperature(u, E)
+    err = {"rho": float(np.max(np.abs(r - r_o) / r_o)),
+           "u": float(np.max(np.abs(u - u_o)) / np.max(np.abs(u_o))),
+           "T": float(np.max(np.abs(T - T_o) / T_o))}
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": round(cells * steps / dt / 1e6, 3), "unit": "MLUPS",
+            "cores": num_threads(), "kind": "oracle",
+            "sample": f"FP64 oracle, D{dim}Q{o.Q} "
+                      f"{'x'.join(str(v) for v in shape[:dim])} periodic, same recipe and "
+                      f"parameters as the headline, {steps} steps ({dt:.1f} s)",
+            "cpu_model": cpu_model, "gpu_vs_oracle_max_rel_err": err}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--path", default="d3q107_fp32", choices=sorted(PATHS))
+    ap.add_argument("--no-extra", action="store_true", help="skip the other three paths")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the solver has no multi-GPU path "
+              "(sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    head = PATHS[args.path]
+    res = run_path(args.path, head, args.steps, args.warmup)
+    print(f"# {args.path}: {res['mlups']} MLUPS, {res['gbs']} GB/s", file=sys.stderr, flush=True)
+    paths = {args.path: res}
+    if not args.no_extra:
+        for name, p in PATHS.items():
+            if name == args.path:
+                continue
+            paths[name] = run_path(name, p, p["steps"], args.warmup)
+            print(f"# {name}: {paths[name]['mlups']} MLUPS, {paths[name]['gbs']} GB/s",
+                  file=sys.stderr, flush=True)
+    traffic = res["traffic_bytes_per_launch"]
+    out = {
+        "metric": "MLUPS (million lattice-cell updates per second)",
+        "value": res["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp32" if head["fp32"] else "fp64", "data": "synthetic",
+        "config": {"workload": res["workload"], "grid": list(head["shape"][:head["dim"]]),
+                   "velocity_set": f"D{head['dim']}Q{37 if head['dim'] == 2 else 107}",
+                   "storage": "fp32 deviation" if head["fp32"] else "fp64",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": res["gbs"], "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": res["hbm_frac"],
+                     "traffic": traffic, "bytes_per_update": res["bytes_per_update"],
+                     "kernel": "k_step_split (fused pull, moments, equilibrium, relax, store)"},
+        "paths": {k: {kk: v[kk] for kk in ("workload", "mlups", "gbs", "hbm_frac",
+                                            "ms_per_step", "steps")}
+                  for k, v in paths.items()},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(head)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

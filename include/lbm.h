@@ -1,0 +1,170 @@
+/*
+ * liblbm -- MI355X (gfx950) implementation of the thermal lattice Boltzmann
+ * scheme with arbitrary specific-heat ratio of Hu, Zhang & Geng
+ * (arXiv:1608.06345): two reduced distributions per cell, g (mass and
+ * momentum) and h (internal energy), on the D2Q37 and D3Q107 velocity sets,
+ * advanced by a fused BGK collide-and-stream step.
+ *
+ * The method, section by section:
+ *   Sec. II   the reduced distributions g and h; the moments
+ *             rho = sum g_i, rho u = sum g_i xi_i,
+ *             rho E = sum xi_i^2 g_i / 2 + sum h_i;
+ *             the specific-heat ratio gamma = (delta + D + 2) / (delta + D)
+ *             through delta internal degrees of freedom; the dimensionless
+ *             energy E = u^2/2 + (D + delta) T / 2; the BGK targets
+ *             F_i (for g) and (delta/2) T F_i (for h).
+ *   Sec. III  explicit first-order time stepping of both BGK equations.
+ *   Sec. IV   the fourth-order Hermite equilibrium F_i and the velocity sets
+ *             (Table I: D2Q37, Table II: D3Q107, xi_i = r e_i, r ~ 1.19698).
+ *   Sec. V    the shock-tube set-up: periodic transverse axes, open ends
+ *             along x, and the lattice time conversion t = step / (X r),
+ *             i.e. every population moves e_i cells per step.
+ *
+ * Conventions shared by every call
+ *   - Every call returns an lbm_status code; nothing aborts or throws.
+ *   - Cell index = x + nx * (y + ny * z); 2D grids have nz = 1.
+ *   - Host arrays are owned and allocated by the caller; the library copies
+ *     them synchronously.  "_dev" variants take device pointers and run
+ *     asynchronously on the handle's stream.
+ *   - Vector fields are component-major: u[k * ncells + cell].
+ *   - All device memory of a solve is owned by the library; it is released
+ *     by lbm_destroy.
+ *   - A handle is not thread-safe; separate handles are independent.
+ *   - State convention: S_0 is the equilibrium of the initial fields and one
+ *     step is S_{n+1} = Stream(Collide(S_n)).  lbm_moments and lbm_totals
+ *     report S_n, the pre-collision state after n steps.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_solver *lbm_handle;
+
+enum lbm_status {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,     /* invalid argument (see each call) */
+    LBM_ENOMEM = -2,     /* device allocation failed */
+    LBM_EDEVICE = -3,    /* a HIP runtime call failed */
+    LBM_ESTATE = -4,     /* call out of order (e.g. step before init) */
+    LBM_ENONFINITE = -5  /* a conservation total is NaN or infinite */
+};
+
+enum lbm_velocity_set { LBM_D2Q37 = 37, LBM_D3Q107 = 107 };
+
+/* Boundary condition per axis, 2 bits each: bc = bx | by << 2 | bz << 4.
+ * PERIODIC wraps.  ZERO_GRADIENT is the reading of the paper's "open"
+ * boundary (Sec. V): populations streaming in from beyond the end are the
+ * post-collision populations of the end cell (pull source clamped). */
+enum lbm_bc { LBM_BC_PERIODIC = 0, LBM_BC_ZERO_GRADIENT = 1 };
+#define LBM_BC(bx, by, bz) \
+    ((uint32_t)(bx) | ((uint32_t)(by) << 2) | ((uint32_t)(bz) << 4))
+
+/* Storage and arithmetic precision of the populations.
+ * FP64: populations and collision in double.
+ * FP32_DEV: populations stored in float as deviations from the rest
+ *   equilibrium, g_i - w_i and h_i - w_i delta/2 (reference rho0 = T0 = 1),
+ *   collision in float computed directly on the deviations; readouts and
+ *   conservation totals in double. */
+enum lbm_precision { LBM_FP64 = 0, LBM_FP32_DEV = 1 };
+
+/* Create a solve (Secs. II-IV).
+ *   dim           2 or 3
+ *   velocity_set  LBM_D2Q37 with dim 2, LBM_D3Q107 with dim 3
+ *   gamma         specific-heat ratio; delta = 2/(gamma-1) - dim, values
+ *                 within 1e-9 of 0 taken as 0; delta < 0 is rejected
+ *   tau_f, tau_g  relaxation times of g and h in lattice units (> 1/2).
+ *                 The paper uses one tau for both (Sec. II); two different
+ *                 values conserve mass and momentum but not total energy.
+ *   nx, ny, nz    grid size (>= 1; nz must be 1 when dim is 2)
+ *   bc            LBM_BC(bx, by, bz)
+ *   out           receives the handle
+ * Errors: EINVAL for any argument outside the above, or a grid whose one
+ * population array exceeds 2^31 - 1 bytes; ENOMEM if device memory cannot be
+ * allocated; EDEVICE for other HIP failures.  lbm_create uses LBM_FP64. */
+int lbm_create(int dim, int velocity_set, double gamma, double tau_f,
+               double tau_g, int64_t nx, int64_t ny, int64_t nz, uint32_t bc,
+               lbm_handle *out);
+int lbm_create_ex(int dim, int velocity_set, double gamma, double tau_f,
+                  double tau_g, int64_t nx, int64_t ny, int64_t nz,
+                  uint32_t bc, int precision, lbm_handle *out);
+
+/* Release every device resource of the handle (NULL is accepted). */
+int lbm_destroy(lbm_handle h);
+
+/* Run the handle's work on `stream` (a hipStream_t; NULL = the library's own
+ * stream).  The stream is borrowed, not owned. */
+int lbm_set_stream(lbm_handle h, void *stream);
+/* Kernel layout of the fused step (a tuning choice; results agree to
+ * round-off).  LANE: one lane holds all 2Q populations of a cell.  SPLIT: a
+ * lane pair holds them, g in lane l and h in lane l + 32 of the wave.  AUTO
+ * (the default) takes LANE for D2Q37 and SPLIT for D3Q107, whose 214
+ * populations do not fit one lane's registers.  EINVAL for other values. */
+enum lbm_variant { LBM_VARIANT_AUTO = 0, LBM_VARIANT_LANE = 1, LBM_VARIANT_SPLIT = 2 };
+int lbm_set_variant(lbm_handle h, int variant);
+
+/* Block until the handle's stream is idle. */
+int lbm_synchronize(lbm_handle h);
+
+/* Initial state S_0: g_i = F_i(rho, u, T), h_i = (delta/2) T F_i (Sec. II,
+ * Sec. IV), and step count 0.  rho, T: [ncells]; u: [dim][ncells]; FP64 host
+ * arrays.  EINVAL on a NULL pointer. */
+int lbm_init_fields(lbm_handle h, const double *rho, const double *u,
+                    const double *T);
+/* Same from device arrays, asynchronous on the handle's stream; the arrays
+ * must stay valid until the stream reaches this point. */
+int lbm_init_fields_dev(lbm_handle h, const double *rho, const double *u,
+                        const double *T);
+
+/* Advance n >= 0 steps (collide, then stream every population e_i cells),
+ * asynchronously on the handle's stream.  ESTATE before init; EINVAL for
+ * n < 0. */
+int lbm_step(lbm_handle h, int64_t n);
+
+/* Moments of S_n (Sec. II): rho [ncells], u [dim][ncells] and the specific
+ * total energy E = (sum xi^2 g / 2 + sum h) / rho [ncells], in FP64 host
+ * arrays; synchronous.  The temperature follows as
+ * T = (2E - |u|^2) / (dim + delta).  ESTATE before init. */
+int lbm_moments(lbm_handle h, double *rho, double *u, double *E);
+/* Same into device arrays, asynchronous on the handle's stream. */
+int lbm_moments_dev(lbm_handle h, double *rho, double *u, double *E);
+
+/* Domain totals of S_n in FP64: mass = sum rho, mom[k] = sum rho u_k
+ * (mom has dim entries), energy = sum rho E; deterministic summation order.
+ * Synchronous.  ESTATE before init; ENONFINITE (totals still written) if any
+ * total is NaN or infinite. */
+int lbm_totals(lbm_handle h, double *mass, double *mom, double *energy);
+
+/* Read-only facts about a solve. */
+typedef struct {
+    int dim, q, precision;
+    int64_t nx, ny, nz;
+    uint32_t bc;
+    double gamma, delta, tau_f, tau_g, r;
+    int64_t steps;          /* steps taken since the last init */
+    size_t device_bytes;    /* device memory held by the handle */
+} lbm_info;
+int lbm_get_info(lbm_handle h, lbm_info *info);
+
+/* Device bytes a solve of this shape holds (two distributions, two
+ * ping-pong copies, plus reduction scratch); 0 for invalid arguments. */
+size_t lbm_footprint_bytes(int dim, int velocity_set, int precision,
+                           int64_t nx, int64_t ny, int64_t nz);
+
+/* The library's lattice (Sec. IV, Tables I-II): e [q][3] (z = 0 in 2D), w [q]
+ * and the scale r, derived by the library from the Gauss-Hermite moment
+ * conditions.  Any output pointer may be NULL.  Returns q, or EINVAL. */
+int lbm_lattice(int velocity_set, int8_t *e, double *w, double *r);
+
+/* Static description of a status code. */
+const char *lbm_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

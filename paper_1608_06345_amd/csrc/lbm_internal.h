@@ -1,0 +1,104 @@
+// Internal declarations shared by the host runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "lbm.h"
+#include "velocity_set.h"
+
+namespace lbm {
+
+// Lattice constants derived on the host (lattice.cpp).
+struct LatticeTables {
+    int dim, q, groups;
+    double r;
+    double w_group[10];
+    double w[107];
+    int8_t e[107][3];
+    int group[107];
+};
+const LatticeTables& lattice_tables(int dim);
+
+// Group weights by value (kernel argument).
+struct WGroups {
+    double w[10];
+};
+
+// Arguments of the fused step kernel (passed by value in the kernarg
+// segment, so every field is wave-uniform and lives in SGPRs).
+struct StepArgs {
+    const void* src;      // [2][Q][N]: g populations, then h populations
+    void* dst;            // same layout
+    int64_t N;            // cells
+    int32_t nx, ny, nz;
+    int32_t nxy;          // nx * ny
+    uint32_t open_end;    // bit k: axis k is zero-gradient, else periodic
+    int32_t stream;       // 1: pull-stream then collide; 0: collide in place
+    int32_t tiles;        // logical tiles (blocks that do work)
+    int32_t tiles_per_xcd;
+    double omega_f, omega_g;  // 1 / tau
+    double half_delta;        // delta / 2
+    double inv_dof;           // 1 / (D + delta)
+    double r;
+    double w[10];             // group weights
+};
+
+// Arguments of the readout kernel (moments and conservation partials).
+struct ReadArgs {
+    const void* src;
+    int64_t N;
+    int32_t nx, ny, nz, nxy;
+    uint32_t open_end;
+    int32_t stream;           // 1: the source holds P_{n-1}; pull to get S_n
+    double r;
+    double rest_energy;       // (D + delta) / 2, added back in FP32_DEV mode
+    double* rho;              // [N] or null
+    double* u;                // [D][N] or null
+    double* E;                // [N] or null
+    double* partials;         // [blocks][D + 2] or null
+};
+
+// Kernel launchers (kernels.hip).  `split` selects the layout in which one
+// lane holds the g populations of a cell and its partner lane (lane ^ 32)
+// the h populations.
+hipError_t launch_init(int dim, int precision, void* dst, const double* rho,
+                       const double* u, const double* T, int64_t N,
+                       double half_delta, double r, const double* w_group,
+                       hipStream_t s);
+hipError_t launch_step(int dim, int precision, bool split, const StepArgs& a,
+                       hipStream_t s);
+int step_block_cells(int dim, int precision, bool split);
+hipError_t launch_readout(int dim, int precision, const ReadArgs& a,
+                          int blocks, hipStream_t s);
+hipError_t launch_final_reduce(int dim, const double* partials, int blocks,
+                               double* out, hipStream_t s);
+constexpr int kReadBlock = 256;
+
+}  // namespace lbm
+
+// The opaque handle.
+struct lbm_solver {
+    int dim, q, precision;
+    int64_t nx, ny, nz, N;
+    uint32_t bc;
+    double gamma, delta, tau_f, tau_g;
+    const lbm::LatticeTables* lat;
+    size_t elem;          // bytes per stored value
+    size_t buf_bytes;     // bytes of one ping-pong side (2 Q N elem)
+    void* buf[2];         // ping-pong sides
+    int cur;              // side holding the latest post-collision state
+    bool have_state;
+    bool initial;         // buf[cur ^ 1] holds S_0 itself (no step yet)
+    int64_t steps;
+    double* partials;     // readout block partials
+    double* totals;       // [D + 2] final totals (device)
+    int read_blocks;
+    hipStream_t stream;
+    hipStream_t own_stream;
+    int device;
+    bool split;
+    size_t device_bytes;
+};

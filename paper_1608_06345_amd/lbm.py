@@ -1,0 +1,282 @@
+"""Python binding of liblbm (ctypes): argument marshalling only.
+
+Every function here has the name and meaning of the C entry point declared
+in ``include/lbm.h``; all work runs in the HIP library.  Host arrays are
+numpy FP64; device arrays are torch CUDA (HIP) tensors, passed by pointer.
+Importing this module raises if ``liblbm.so`` has not been built -- there is
+no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ESTATE, LBM_ENONFINITE = 0, -1, -2, -3, -4, -5
+LBM_D2Q37, LBM_D3Q107 = 37, 107
+LBM_BC_PERIODIC, LBM_BC_ZERO_GRADIENT = 0, 1
+LBM_FP64, LBM_FP32_DEV = 0, 1
+LBM_VARIANT_AUTO, LBM_VARIANT_LANE, LBM_VARIANT_SPLIT = 0, 1, 2
+
+
+def LBM_BC(bx, by, bz=0):
+    return (bx & 3) | ((by & 3) << 2) | ((bz & 3) << 4)
+
+
+class LBMError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {lbm_strerror(code)} ({code})")
+
+
+class NonFiniteError(LBMError):
+    def __init__(self, code, where, totals):
+        super().__init__(code, where)
+        self.totals = totals
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("q", ctypes.c_int), ("precision", ctypes.c_int),
+                ("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
+                ("bc", ctypes.c_uint32),
+                ("gamma", ctypes.c_double), ("delta", ctypes.c_double),
+                ("tau_f", ctypes.c_double), ("tau_g", ctypes.c_double), ("r", ctypes.c_double),
+                ("steps", ctypes.c_int64), ("device_bytes", ctypes.c_size_t)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_1608_06345_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, d, i64, i32 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int64, ctypes.c_int
+    dp = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "lbm_create": [i32, i32, d, d, d, i64, i64, i64, ctypes.c_uint32, ctypes.POINTER(vp)],
+        "lbm_create_ex": [i32, i32, d, d, d, i64, i64, i64, ctypes.c_uint32, i32,
+                          ctypes.POINTER(vp)],
+        "lbm_destroy": [vp],
+        "lbm_set_stream": [vp, vp],
+        "lbm_set_variant": [vp, i32],
+        "lbm_synchronize": [vp],
+        "lbm_init_fields": [vp, dp, dp, dp],
+        "lbm_init_fields_dev": [vp, vp, vp, vp],
+        "lbm_step": [vp, i64],
+        "lbm_moments": [vp, dp, dp, dp],
+        "lbm_moments_dev": [vp, vp, vp, vp],
+        "lbm_totals": [vp, dp, dp, dp],
+        "lbm_get_info": [vp, ctypes.POINTER(_Info)],
+        "lbm_lattice": [i32, ctypes.POINTER(ctypes.c_int8), dp, dp],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.lbm_footprint_bytes.argtypes = [i32, i32, i32, i64, i64, i64]
+    lib.lbm_footprint_bytes.restype = ctypes.c_size_t
+    lib.lbm_strerror.argtypes = [i32]
+    lib.lbm_strerror.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+def _check(rc, where):
+    if rc != LBM_OK:
+        raise LBMError(rc, where)
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _host(a, n):
+    a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+    if a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a
+
+
+def _dev_ptr(t, n):
+    if not (hasattr(t, "is_cuda") and t.is_cuda):
+        raise TypeError("expected a device (torch CUDA/HIP) tensor")
+    if t.dtype.__repr__() != "torch.float64" or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"expected a contiguous float64 device tensor of {n} values")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def lbm_strerror(code):
+    return _lib.lbm_strerror(int(code)).decode()
+
+
+def lbm_create_ex(dim, velocity_set, gamma, tau_f, tau_g, nx, ny, nz, bc, precision):
+    h = ctypes.c_void_p()
+    _check(_lib.lbm_create_ex(dim, velocity_set, gamma, tau_f, tau_g, nx, ny, nz, bc,
+                              precision, ctypes.byref(h)), "lbm_create_ex")
+    return h
+
+
+def lbm_create(dim, velocity_set, gamma, tau_f, tau_g, nx, ny, nz, bc):
+    h = ctypes.c_void_p()
+    _check(_lib.lbm_create(dim, velocity_set, gamma, tau_f, tau_g, nx, ny, nz, bc,
+                           ctypes.byref(h)), "lbm_create")
+    return h
+
+
+def lbm_create_rc(dim, velocity_set, gamma, tau_f, tau_g, nx, ny, nz, bc,
+                  precision=LBM_FP64):
+    """Raw status code of lbm_create_ex (for error-path tests); destroys a
+    handle that was created."""
+    h = ctypes.c_void_p()
+    rc = _lib.lbm_create_ex(dim, velocity_set, gamma, tau_f, tau_g, nx, ny, nz, bc,
+                            precision, ctypes.byref(h))
+    if rc == LBM_OK:
+        _lib.lbm_destroy(h)
+    return rc
+
+
+def lbm_destroy(h):
+    _check(_lib.lbm_destroy(h), "lbm_destroy")
+
+
+def lbm_set_stream(h, stream):
+    """``stream``: a torch stream, a raw hipStream_t integer, or None."""
+    ptr = getattr(stream, "cuda_stream", stream)
+    _check(_lib.lbm_set_stream(h, ctypes.c_void_p(ptr) if ptr else None), "lbm_set_stream")
+
+
+def lbm_set_variant(h, variant):
+    _check(_lib.lbm_set_variant(h, int(variant)), "lbm_set_variant")
+
+
+def lbm_synchronize(h):
+    _check(_lib.lbm_synchronize(h), "lbm_synchronize")
+
+
+def lbm_get_info(h):
+    info = _Info()
+    _check(_lib.lbm_get_info(h, ctypes.byref(info)), "lbm_get_info")
+    return {name: getattr(info, name) for name, _ in _Info._fields_}
+
+
+def lbm_init_fields(h, rho, u, T):
+    inf = lbm_get_info(h)
+    n = inf["nx"] * inf["ny"] * inf["nz"]
+    rho, u, T = _host(rho, n), _host(u, inf["dim"] * n), _host(T, n)
+    _check(_lib.lbm_init_fields(h, _dp(rho), _dp(u), _dp(T)), "lbm_init_fields")
+
+
+def lbm_init_fields_dev(h, rho, u, T):
+    inf = lbm_get_info(h)
+    n = inf["nx"] * inf["ny"] * inf["nz"]
+    _check(_lib.lbm_init_fields_dev(h, _dev_ptr(rho, n), _dev_ptr(u, inf["dim"] * n),
+                                    _dev_ptr(T, n)), "lbm_init_fields_dev")
+
+
+def lbm_step(h, n):
+    _check(_lib.lbm_step(h, int(n)), "lbm_step")
+
+
+def lbm_moments(h):
+    """(rho [cells], u [dim][cells], E [cells]) of S_n as FP64 numpy arrays."""
+    inf = lbm_get_info(h)
+    n = inf["nx"] * inf["ny"] * inf["nz"]
+    rho, u, E = np.empty(n), np.empty((inf["dim"], n)), np.empty(n)
+    _check(_lib.lbm_moments(h, _dp(rho), _dp(u), _dp(E)), "lbm_moments")
+    return rho, u, E
+
+
+def lbm_moments_dev(h, rho, u, E):
+    inf = lbm_get_info(h)
+    n = inf["nx"] * inf["ny"] * inf["nz"]
+    _check(_lib.lbm_moments_dev(h, _dev_ptr(rho, n), _dev_ptr(u, inf["dim"] * n),
+                                _dev_ptr(E, n)), "lbm_moments_dev")
+
+
+def lbm_totals(h):
+    """(mass, momentum [dim], energy); NonFiniteError if any is NaN/Inf."""
+    inf = lbm_get_info(h)
+    mass, energy = np.zeros(1), np.zeros(1)
+    mom = np.zeros(3)
+    rc = _lib.lbm_totals(h, _dp(mass), _dp(mom), _dp(energy))
+    out = (float(mass[0]), mom[:inf["dim"]].copy(), float(energy[0]))
+    if rc == LBM_ENONFINITE:
+        raise NonFiniteError(rc, "lbm_totals", out)
+    _check(rc, "lbm_totals")
+    return out
+
+
+def lbm_footprint_bytes(dim, velocity_set, precision, nx, ny, nz):
+    return int(_lib.lbm_footprint_bytes(dim, velocity_set, precision, nx, ny, nz))
+
+
+def lbm_lattice(velocity_set):
+    """(e [q][3] int8, w [q] FP64, r) of the library's lattice."""
+    q = _lib.lbm_lattice(velocity_set, None, None, None)
+    if q < 0:
+        raise LBMError(q, "lbm_lattice")
+    e = np.zeros((q, 3), dtype=np.int8)
+    w = np.zeros(q)
+    r = np.zeros(1)
+    _lib.lbm_lattice(velocity_set, e.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), _dp(w),
+                     _dp(r))
+    return e, w, float(r[0])
+
+
+class Solver:
+    """One solve behind a handle; closes it on ``close()`` / exit."""
+
+    def __init__(self, dim, gamma, tau_f, tau_g, nx, ny, nz=1, bc=0, precision=LBM_FP64):
+        vs = LBM_D2Q37 if dim == 2 else LBM_D3Q107
+        self.h = lbm_create_ex(dim, vs, gamma, tau_f, tau_g, nx, ny, nz, bc, precision)
+        self.dim = dim
+        self.ncells = nx * ny * nz
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def close(self):
+        if self.h is not None:
+            lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def info(self):
+        return lbm_get_info(self.h)
+
+    def init_fields(self, rho, u, T):
+        lbm_init_fields(self.h, rho, u, T)
+
+    def step(self, n=1):
+        lbm_step(self.h, n)
+
+    def moments(self):
+        return lbm_moments(self.h)
+
+    def temperature(self, u, E):
+        inf = self.info
+        return (2.0 * E - np.sum(np.asarray(u) ** 2, axis=0)) / (inf["dim"] + inf["delta"])
+
+    def totals(self):
+        return lbm_totals(self.h)
+
+    def synchronize(self):
+        lbm_synchronize(self.h)
+
+    def set_stream(self, stream):
+        lbm_set_stream(self.h, stream)
+
+    def set_variant(self, variant):
+        lbm_set_variant(self.h, variant)

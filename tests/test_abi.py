@@ -1,0 +1,89 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point that include/lbm.h declares, derives the same lattice as
+the oracle (independently), sizes footprints, and rejects invalid arguments
+before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1608_06345_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for f in os.listdir(os.path.join(ROOT, "include")):
+        if f.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", f)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(lbm_\w+)\s*\(", text, re.M))
+    return names
+
+
+def test_every_declared_symbol_is_exported():
+    names = _declared()
+    assert {"lbm_create", "lbm_init_fields", "lbm_step", "lbm_moments"} <= names
+    lib = ctypes.CDLL(lbm.LIB_PATH)
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+
+
+@pytest.mark.parametrize("dim,vs", [(2, 37), (3, 107)])
+def test_library_lattice_matches_oracle(dim, vs):
+    from oracle.lattice import lattice
+    e, w, r = lbm.lbm_lattice(vs)
+    lat = lattice(dim)
+    assert e.shape == (vs, 3) and abs(r - lat.r) <= 2e-16
+    if dim == 2:
+        assert np.all(e[:, 2] == 0)
+    mine = {tuple(int(a) for a in v[:dim]): x for v, x in zip(e, w)}
+    assert len(mine) == vs
+    for v, x in zip(lat.e, lat.w):
+        assert abs(mine[tuple(int(a) for a in v)] - x) <= 4e-16 * x
+    # rest first, then opposite pairs next to each other
+    assert np.all(e[0] == 0)
+    assert np.all(e[1::2] == -e[2::2])
+
+
+def test_footprint():
+    fp = lbm.lbm_footprint_bytes(3, 107, lbm.LBM_FP32_DEV, 256, 256, 256)
+    assert fp >= 2 * 2 * 107 * 256 ** 3 * 4
+    assert fp < 1.01 * 2 * 2 * 107 * 256 ** 3 * 4
+    assert lbm.lbm_footprint_bytes(3, 107, lbm.LBM_FP64, 256, 256, 256) > 1.99 * fp
+    assert lbm.lbm_footprint_bytes(2, 107, 0, 4, 4, 1) == 0
+    assert lbm.lbm_footprint_bytes(2, 37, 0, 4, 4, 2) == 0
+
+
+@pytest.mark.parametrize("args", [
+    (2, 107, 1.4, 0.7, 0.7, 8, 8, 1, 0),        # dim / velocity set mismatch
+    (3, 37, 1.4, 0.7, 0.7, 8, 8, 8, 0),
+    (4, 37, 1.4, 0.7, 0.7, 8, 8, 1, 0),
+    (2, 37, 1.4, 0.5, 0.7, 8, 8, 1, 0),         # tau <= 1/2
+    (2, 37, 1.4, 0.7, 0.4, 8, 8, 1, 0),
+    (2, 37, 1.0, 0.7, 0.7, 8, 8, 1, 0),         # gamma <= 1
+    (3, 107, 1.7, 0.7, 0.7, 8, 8, 8, 0),        # delta < 0
+    (2, 37, 2.1, 0.7, 0.7, 8, 8, 1, 0),
+    (2, 37, 1.4, 0.7, 0.7, 0, 8, 1, 0),         # empty grid
+    (2, 37, 1.4, 0.7, 0.7, 8, 8, 2, 0),         # nz != 1 in 2D
+    (2, 37, 1.4, 0.7, 0.7, 8, 8, 1, 2),         # unknown bc code
+    (2, 37, 1.4, 0.7, 0.7, 8, 8, 1, 1 << 4),    # z bc in 2D
+    (2, 37, 1.4, 0.7, 0.7, 8, 8, 1, 1 << 7),
+    (3, 107, 1.4, 0.7, 0.7, 1024, 1024, 1024, 0),  # plane beyond 2^31 bytes
+])
+def test_create_rejects_invalid_arguments(args):
+    assert lbm.lbm_create_rc(*args) == lbm.LBM_EINVAL
+    assert lbm.lbm_create_rc(*args, precision=lbm.LBM_FP32_DEV) == lbm.LBM_EINVAL
+
+
+def test_invalid_precision_and_null_handles():
+    assert lbm.lbm_create_rc(2, 37, 1.4, 0.7, 0.7, 8, 8, 1, 0, precision=7) == lbm.LBM_EINVAL
+    lib = lbm._lib
+    assert lib.lbm_step(None, 1) == lbm.LBM_EINVAL
+    assert lib.lbm_destroy(None) == lbm.LBM_OK
+    assert lib.lbm_set_variant(None, 0) == lbm.LBM_EINVAL
+    assert lbm.lbm_strerror(lbm.LBM_ENONFINITE).startswith("non-finite")
+    assert lbm.lbm_strerror(12345) == "unknown status"

@@ -1,0 +1,203 @@
+"""GPU (HIP, through the C ABI) versus the FP64 oracle on identical seeded
+inputs.  Bars: FP64 1e-12 and FP32 deviation storage 1e-5 max relative error
+in rho, u and T (u relative to its field maximum) on smooth fields after
+1000 steps; grids span several 256-cell tiles and end in a ragged tile."""
+import numpy as np
+import pytest
+
+from paper_1608_06345_amd import lbm
+from paper_1608_06345_amd.inputs import smooth_fields, sod_fields, uniform_fields
+from parity_util import (TOL_FP32, TOL_FP64, assert_close, gpu_run, open_of,
+                         oracle_run)
+
+pytestmark = pytest.mark.gpu
+
+P64, P32 = lbm.LBM_FP64, lbm.LBM_FP32_DEV
+LANE, SPLIT = lbm.LBM_VARIANT_LANE, lbm.LBM_VARIANT_SPLIT
+
+
+@pytest.fixture(scope="module")
+def smooth2d():
+    shape = (61, 53, 1)  # 3233 cells: 12 full tiles + a ragged one
+    return shape, smooth_fields(2, *shape, seed=2)
+
+
+@pytest.fixture(scope="module")
+def smooth3d():
+    shape = (23, 19, 17)
+    return shape, smooth_fields(3, *shape, seed=3)
+
+
+@pytest.fixture(scope="module")
+def oracle2d(smooth2d):
+    shape, f = smooth2d
+    return oracle_run(2, 1.4, 0.7, 0.8, shape, f, 1000)
+
+
+@pytest.fixture(scope="module")
+def oracle3d(smooth3d):
+    shape, f = smooth3d
+    return oracle_run(3, 1.4, 0.65, 0.65, shape, f, 1000)
+
+
+@pytest.mark.parametrize("precision,variant,tol", [(P64, LANE, TOL_FP64), (P64, SPLIT, TOL_FP64),
+                                                   (P32, LANE, TOL_FP32), (P32, SPLIT, TOL_FP32)])
+def test_2d_smooth_1000_steps(smooth2d, oracle2d, precision, variant, tol):
+    shape, f = smooth2d
+    g = gpu_run(2, 1.4, 0.7, 0.8, shape, f, 1000, precision=precision, variant=variant)
+    e = assert_close(g, oracle2d, tol, "D2Q37")
+    print("D2Q37", precision, variant, e)
+
+
+@pytest.mark.parametrize("precision,variant,tol", [(P64, SPLIT, TOL_FP64), (P32, SPLIT, TOL_FP32),
+                                                   (P32, LANE, TOL_FP32)])
+def test_3d_smooth_1000_steps(smooth3d, oracle3d, precision, variant, tol):
+    shape, f = smooth3d
+    g = gpu_run(3, 1.4, 0.65, 0.65, shape, f, 1000, precision=precision, variant=variant)
+    e = assert_close(g, oracle3d, tol, "D3Q107")
+    print("D3Q107", precision, variant, e)
+
+
+@pytest.mark.parametrize("dim,gamma,tf,tg", [(3, 5.0 / 3.0, 0.65, 0.65), (2, 2.0, 0.6, 0.9),
+                                             (3, 1.25, 0.9, 0.6)])
+@pytest.mark.parametrize("precision,tol", [(P64, TOL_FP64), (P32, TOL_FP32)])
+def test_gamma_and_two_tau(dim, gamma, tf, tg, precision, tol):
+    # delta = 0 (h carries nothing), and tau_f != tau_g, where the reported
+    # state convention (moments of S_n, not of the post-collision state)
+    # changes E
+    shape = (13, 11, 9) if dim == 3 else (37, 29, 1)
+    f = smooth_fields(dim, *shape, seed=11, a_rho=0.03, a_u=0.05, a_T=0.03)
+    o = oracle_run(dim, gamma, tf, tg, shape, f, 150)
+    g = gpu_run(dim, gamma, tf, tg, shape, f, 150, precision=precision)
+    assert_close(g, o, tol, f"gamma {gamma}")
+
+
+@pytest.mark.parametrize("steps", [0, 1, 2, 7])
+@pytest.mark.parametrize("precision,tol", [(P64, TOL_FP64), (P32, TOL_FP32)])
+def test_first_steps(steps, precision, tol):
+    shape = (19, 7, 1)
+    f = smooth_fields(2, *shape, seed=5, a_rho=0.05, a_u=0.05, a_T=0.05)
+    o = oracle_run(2, 1.4, 0.7, 0.8, shape, f, steps)
+    g = gpu_run(2, 1.4, 0.7, 0.8, shape, f, steps, precision=precision)
+    assert_close(g, o, tol, f"{steps} steps")
+    if steps == 0:  # moments of S_0 are the initial fields themselves
+        t_rho, t_T = (1e-14, 1e-13) if precision == P64 else (1e-7, 1e-6)
+        assert np.max(np.abs(g[0] - f[0])) < t_rho
+        assert np.max(np.abs(g[2] - f[2])) < t_T
+
+
+@pytest.mark.parametrize("dim,shape,bc", [
+    (2, (1, 1, 1), 0), (2, (2, 3, 1), 0), (2, (5, 1, 1), 0), (2, (4, 4, 1), lbm.LBM_BC(1, 1)),
+    (2, (1, 6, 1), lbm.LBM_BC(0, 1)), (3, (1, 1, 1), 0), (3, (3, 2, 1), 0),
+    (3, (7, 6, 5), lbm.LBM_BC(1, 1, 1)), (3, (9, 2, 4), lbm.LBM_BC(1, 0, 1)),
+    (3, (2, 5, 3), lbm.LBM_BC(0, 1, 0))])
+@pytest.mark.parametrize("precision,tol", [(P64, TOL_FP64), (P32, TOL_FP32)])
+def test_tiny_and_open_grids(dim, shape, bc, precision, tol):
+    f = smooth_fields(dim, *shape, seed=13, a_rho=0.05, a_u=0.05, a_T=0.05)
+    o = oracle_run(dim, 1.4, 0.7, 0.75, shape, f, 12, open_end=open_of(bc))
+    g = gpu_run(dim, 1.4, 0.7, 0.75, shape, f, 12, bc=bc, precision=precision)
+    assert_close(g, o, tol, f"{shape} bc={bc}")
+
+
+@pytest.mark.parametrize("precision", [P64, P32])
+def test_sod_shock_tube(precision):
+    # Sod tube, 200 x 4, zero-gradient ends in x, periodic y, tau 0.6
+    from oracle.riemann import l1_errors, shock_tube_profile
+    shape = (200, 4, 1)
+    bc = lbm.LBM_BC(lbm.LBM_BC_ZERO_GRADIENT, lbm.LBM_BC_PERIODIC)
+    f = sod_fields(2, *shape)
+    tol = TOL_FP64 if precision == P64 else 1e-4
+    for steps in (48, 250):
+        o = oracle_run(2, 1.4, 0.6, 0.6, shape, f, steps, open_end=(True, False, False))
+        g = gpu_run(2, 1.4, 0.6, 0.6, shape, f, steps, bc=bc, precision=precision)
+        # absolute u error: the tube starts at rest
+        e_rho = np.max(np.abs(g[0] - o[0]) / o[0])
+        e_T = np.max(np.abs(g[2] - o[2]) / o[2])
+        e_u = np.max(np.abs(g[1] - o[1]))
+        assert max(e_rho, e_T, e_u) < tol, (steps, e_rho, e_u, e_T)
+        if steps == 48:
+            rho, u, T = g[0][:200], g[1][0][:200], g[2][:200]
+            l1 = l1_errors(rho, u, rho * T,
+                           *shock_tube_profile((1, 0, 1), (0.125, 0, 0.1), 1.4, 200, 48,
+                                               lbm.lbm_lattice(37)[2]))
+            assert l1[0] < 0.01 and l1[1] < 0.02 and l1[2] < 0.01, l1
+        for y in range(1, 4):  # quasi-1D: rows identical
+            assert np.array_equal(g[0][y * 200:(y + 1) * 200], g[0][:200])
+
+
+def test_totals_match_oracle_and_conserve():
+    shape = (45, 38, 1)
+    f = smooth_fields(2, *shape, seed=8, a_rho=0.05, a_u=0.05, a_T=0.05)
+    o = oracle_run(2, 1.4, 0.7, 0.7, shape, f, 100)
+    g = gpu_run(2, 1.4, 0.7, 0.7, shape, f, 100)
+    (mo, po, eo), (mg, pg, eg) = o[3], g[3]
+    assert mg == pytest.approx(mo, rel=1e-13)
+    assert np.allclose(pg, po, rtol=0, atol=1e-11)
+    assert eg == pytest.approx(eo, rel=1e-13)
+    g0 = gpu_run(2, 1.4, 0.7, 0.7, shape, f, 0)
+    assert mg == pytest.approx(g0[3][0], rel=1e-13)
+    assert eg == pytest.approx(g0[3][2], rel=1e-13)
+
+
+@pytest.mark.parametrize("dim,precision", [(2, P64), (2, P32), (3, P64), (3, P32)])
+def test_deterministic(dim, precision):
+    shape = (40, 9, 1) if dim == 2 else (11, 7, 6)
+    f = smooth_fields(dim, *shape, seed=21)
+    a = gpu_run(dim, 1.4, 0.7, 0.8, shape, f, 30, precision=precision)
+    b = gpu_run(dim, 1.4, 0.7, 0.8, shape, f, 30, precision=precision)
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x, y)
+    assert a[3][0] == b[3][0] and a[3][2] == b[3][2]
+
+
+def test_uniform_fixed_point_gpu():
+    for dim, shape in ((2, (33, 10, 1)), (3, (9, 8, 7))):
+        f = uniform_fields(dim, *shape, rho=1.2, u=(0.03, -0.01, 0.02), T=0.9)
+        for precision, tol in ((P64, 1e-13), (P32, 1e-6)):
+            g = gpu_run(dim, 1.4, 0.7, 0.8, shape, f, 20,
+                        bc=lbm.LBM_BC(1, 0, 1 if dim == 3 else 0), precision=precision)
+            assert np.max(np.abs(g[0] - 1.2)) < tol
+            assert np.max(np.abs(g[2] - 0.9)) < tol
+
+
+def test_state_errors_and_nonfinite():
+    with lbm.Solver(2, 1.4, 0.7, 0.7, 8, 8) as s:
+        with pytest.raises(lbm.LBMError) as ei:
+            s.step(1)
+        assert ei.value.code == lbm.LBM_ESTATE
+        with pytest.raises(lbm.LBMError):
+            s.moments()
+        with pytest.raises(lbm.LBMError):
+            lbm.lbm_step(s.h, -1)
+        rho, u, T = uniform_fields(2, 8, 8)
+        rho[17] = np.nan
+        s.init_fields(rho, u, T)
+        s.step(3)
+        with pytest.raises(lbm.NonFiniteError):
+            s.totals()
+
+
+def test_device_arrays_and_torch_stream():
+    import torch
+    shape = (50, 21, 1)
+    n = shape[0] * shape[1]
+    f = smooth_fields(2, *shape, seed=4)
+    o = oracle_run(2, 1.4, 0.7, 0.8, shape, f, 40)
+    dev = torch.device("cuda:0")
+    rho, u, T = (torch.tensor(a, dtype=torch.float64, device=dev).contiguous() for a in f)
+    out = [torch.empty(n, dtype=torch.float64, device=dev),
+           torch.empty(2 * n, dtype=torch.float64, device=dev),
+           torch.empty(n, dtype=torch.float64, device=dev)]
+    stream = torch.cuda.Stream()
+    with lbm.Solver(2, 1.4, 0.7, 0.8, *shape) as s:
+        s.set_stream(stream)
+        with torch.cuda.stream(stream):
+            lbm.lbm_init_fields_dev(s.h, rho, u.reshape(-1), T)
+            s.step(40)
+            lbm.lbm_moments_dev(s.h, *out)
+        stream.synchronize()
+        rg = out[0].cpu().numpy()
+        ug = out[1].cpu().numpy().reshape(2, n)
+        Eg = out[2].cpu().numpy()
+        Tg = s.temperature(ug, Eg)
+    assert_close((rg, ug, Tg), o, TOL_FP64, "device arrays")
