@@ -89,7 +89,10 @@ lbm::StepArgs step_args(const lbm_solver* h, const void* src, void* dst, bool st
     a.half_delta = 0.5 * h->delta;
     a.inv_dof = 1.0 / (h->dim + h->delta);
     a.r = h->lat->r;
-    for (int g = 0; g < h->lat->groups; ++g) a.w[g] = h->lat->w_group[g];
+    for (int g = 0; g < h->lat->groups; ++g) {
+        a.w[g] = h->lat->w_group[g];
+        a.wf[g] = (float)h->lat->w_group[g];
+    }
     return a;
 }
 

@@ -37,13 +37,16 @@ struct StepArgs {
     int32_t nxy;          // nx * ny
     uint32_t open_end;    // bit k: axis k is zero-gradient, else periodic
     int32_t stream;       // 1: pull-stream then collide; 0: collide in place
-    int32_t tiles;        // logical tiles (blocks that do work)
+    int32_t segs;         // row segments per row (one wave each)
+    int32_t items;        // row segments in the grid
+    int32_t tiles;        // logical workgroups (four segments each)
     int32_t tiles_per_xcd;
     double omega_f, omega_g;  // 1 / tau
     double half_delta;        // delta / 2
     double inv_dof;           // 1 / (D + delta)
     double r;
     double w[10];             // group weights
+    float wf[10];             // the same, rounded to float
 };
 
 // Arguments of the readout kernel (moments and conservation partials).

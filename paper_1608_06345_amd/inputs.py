@@ -93,3 +93,24 @@ def uniform_fields(dim, nx, ny, nz=1, rho=1.0, u=(0.0, 0.0, 0.0), T=1.0):
     for c in range(dim):
         uu[c] = u[c]
     return np.full(n, float(rho)), uu, np.full(n, float(T))
+
+
+def shear_wave_fields(dim, nx, ny, nz=1, seed=0, amp=0.05, background=0.25):
+    """Long transverse (shear) and longitudinal waves along x with seeded
+    phases, on top of the ``smooth`` recipe scaled by ``background``.  The
+    waves span the whole x extent, so viscosity damps them slowly and the
+    flow is still of useful size after thousands of steps; the background
+    modes give every lattice direction work to do early on."""
+    if dim == 2:
+        nz = 1
+    rho, u, T = smooth_fields(dim, nx, ny, nz, seed=seed, a_rho=0.01 * background,
+                              a_u=0.02 * background, a_T=0.01 * background)
+    rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(4)[3])
+    ph = rng.uniform(0.0, 2.0 * math.pi, 4)
+    x = (np.arange(nx * ny * nz) % nx) / nx
+    u[1] += amp * np.sin(2 * math.pi * x + ph[0])
+    if dim == 3:
+        u[2] += 0.6 * amp * np.cos(2 * math.pi * x + ph[1])
+    rho += 0.2 * amp * np.cos(2 * math.pi * x + ph[2])
+    T += 0.2 * amp * np.cos(2 * math.pi * x + ph[3])
+    return rho, u, T

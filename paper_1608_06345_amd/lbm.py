@@ -11,6 +11,15 @@ import os
 
 import numpy as np
 
+# One HIP runtime per process: PyTorch ships its own libamdhip64 with the
+# same soname as the system one liblbm links against.  Loading torch first
+# makes liblbm bind to the runtime torch already holds; the other order
+# would bring up a second runtime, and torch's would then see no GPU.
+try:
+    import torch  # noqa: F401
+except ImportError:  # torch is optional for host-array use of the library
+    torch = None
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
