@@ -56,15 +56,16 @@ def describe(name, p):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "velocity_set.h", "lbm_internal.h"):
+    for f in ("kernels.hip", "velocity_set.h", "lbm_internal.h", "api.hip"):
         with open(os.path.join(ROOT, "paper_1608_06345_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 def measured_traffic(name, cells):
-    """HBM bytes per launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source; else None."""
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known
+    size), if it was taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -88,10 +89,11 @@ def run_path(name, p, steps, warmup):
     cells = nx * ny * nz
     prec = lbm.LBM_FP32_DEV if p["fp32"] else lbm.LBM_FP64
     f = smooth_fields(p["dim"], nx, ny, nz, seed=p["seed"])
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()  # the kernels' stream; the events go on it too
     with lbm.Solver(p["dim"], p["gamma"], p["tf"], p["tg"], nx, ny, nz, precision=prec) as s:
         s.set_stream(stream)
         dev = [torch.from_numpy(a.reshape(-1)).to("cuda") for a in f]
+        torch.cuda.synchronize()
         lbm.lbm_init_fields_dev(s.h, *dev)
         s.step(warmup)
         torch.cuda.synchronize()
@@ -135,7 +137,7 @@ def cpu_baseline(p, seconds_hint=15.0):
     n = 64
     dim = p["dim"]
     shape = (n, n, n) if dim == 3 else (4 * n, 4 * n, 1)
-    steps = 50
+    steps = 150
     f = smooth_fields(dim, *shape, seed=p["seed"])
     o = OracleLBM(dim, p["gamma"], p["tf"], p["tg"], *shape)
     o.init_fields(*f)
@@ -179,7 +181,19 @@ def main():
     ap.add_argument("--path", default="d3q107_fp32", choices=sorted(PATHS))
     ap.add_argument("--no-extra", action="store_true", help="skip the other three paths")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only copy a device buffer of BYTES bytes 5 times (a plain copy "
+                         "kernel of known size, to scale the HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        a = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe, "launches": 5}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the solver has no multi-GPU path "
               "(sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
@@ -212,7 +226,13 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": res["gbs"], "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": res["hbm_frac"],
-                     "traffic": traffic, "bytes_per_update": res["bytes_per_update"],
+                     # counter-measured HBM bytes per launch over the live
+                     # average launch time (null if the kernel changed since)
+                     "traffic": (round(traffic / (res["ms_per_step"] * 1e-3) / 1e9, 1)
+                                 if traffic else None),
+                     "traffic_bytes_per_launch": traffic,
+                     "algorithmic_bytes_per_launch": res["bytes_per_update"] * res["cells"],
+                     "bytes_per_update": res["bytes_per_update"],
                      "kernel": "k_step_split (fused pull, moments, equilibrium, relax, store)"},
         "paths": {k: {kk: v[kk] for kk in ("workload", "mlups", "gbs", "hbm_frac",
                                             "ms_per_step", "steps")}

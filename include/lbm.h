@@ -97,8 +97,9 @@ int lbm_create_ex(int dim, int velocity_set, double gamma, double tau_f,
 /* Release every device resource of the handle (NULL is accepted). */
 int lbm_destroy(lbm_handle h);
 
-/* Run the handle's work on `stream` (a hipStream_t; NULL = the library's own
- * stream).  The stream is borrowed, not owned. */
+/* Run the handle's work on `stream` (a hipStream_t; NULL is the device's
+ * null stream).  Until this is called a handle uses a non-blocking stream of
+ * its own.  The stream is borrowed, not owned: it must outlive its use. */
 int lbm_set_stream(lbm_handle h, void *stream);
 /* Kernel layout of the fused step (a tuning choice; results agree to
  * round-off).  LANE: one lane holds all 2Q populations of a cell.  SPLIT: a

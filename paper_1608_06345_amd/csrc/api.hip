@@ -243,7 +243,7 @@ int lbm_destroy(lbm_handle h) {
 
 int lbm_set_stream(lbm_handle h, void* stream) {
     if (!h) return LBM_EINVAL;
-    h->stream = stream ? static_cast<hipStream_t>(stream) : h->own_stream;
+    h->stream = static_cast<hipStream_t>(stream);
     return LBM_OK;
 }
 

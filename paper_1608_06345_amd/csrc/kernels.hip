@@ -18,12 +18,28 @@
 //   4. relax  g_i' = g_i + (F_i - g_i)/tau_f,
 //             h_i' = h_i + ((delta/2) T F_i - h_i)/tau_g;
 //   5. store  g_i', h_i' at x (coalesced).
+#include <tuple>
 #include <type_traits>
+#include <utility>
 
 #include "lbm_internal.h"
 
 namespace lbm {
 namespace {
+
+// Launch with the launch's own status (hipLaunchKernel), so that an error
+// left behind by unrelated work in the process is not taken for ours.
+template <typename... KArgs, typename... Args>
+hipError_t launch_kernel(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStream_t s,
+                         Args&&... args) {
+    std::tuple<std::decay_t<KArgs>...> vals(std::forward<Args>(args)...);
+    void* ptrs[sizeof...(KArgs) > 0 ? sizeof...(KArgs) : 1];
+    std::apply([&](auto&... v) {
+        int i = 0;
+        ((ptrs[i++] = static_cast<void*>(&v)), ...);
+    }, vals);
+    return hipLaunchKernel(reinterpret_cast<const void*>(kernel), grid, block, ptrs, 0, s);
+}
 
 template <int B, int E, typename F>
 __device__ __forceinline__ void static_for(F&& f) {
@@ -38,9 +54,12 @@ __device__ __forceinline__ T load_at(const char* base, uint32_t byte_off) {
     return *reinterpret_cast<const T*>(base + byte_off);
 }
 
+// Populations are written once per step and read back only in the next
+// launch, far beyond what L2 holds: stream them out non-temporally so they do
+// not evict the lines that neighbouring waves are still pulling from.
 template <typename T>
 __device__ __forceinline__ void store_at(char* base, uint32_t byte_off, T v) {
-    *reinterpret_cast<T*>(base + byte_off) = v;
+    __builtin_nontemporal_store(v, reinterpret_cast<T*>(base + byte_off));
 }
 
 // Source coordinate of a pull along one axis: x - e, wrapped (periodic) or
@@ -76,13 +95,6 @@ struct PullTable {
     }
 };
 
-// Logical tile of this workgroup.  Workgroups are dispatched to the eight
-// XCDs round-robin by id; this gives each XCD one contiguous range of tiles,
-// so the x-neighbour lines that shifted reads share land in the same L2.
-__device__ __forceinline__ int logical_tile(int tiles_per_xcd) {
-    const int b = blockIdx.x;
-    return (b & 7) * tiles_per_xcd + (b >> 3);
-}
 
 // Cell -> (x, y, z).
 __device__ __forceinline__ void coords(int cell, int nx, int nxy, int& x, int& y,
@@ -316,11 +328,30 @@ struct RowOffsets {
 template <int D, typename T, int L>
 __device__ __forceinline__ bool row_item(const StepArgs& a, int lane_cell, uint32_t role_off,
                                          RowOffsets<T>& o, bool& active) {
-    const int blk = logical_tile(a.tiles_per_xcd);
-    const int item = __builtin_amdgcn_readfirstlane(blk * 4 + (int)(threadIdx.x >> 6));
-    if (item >= a.items) return false;
-    const int seg = item % a.segs;
-    const int row = item / a.segs;
+    // Which row segment this wave serves.  The hardware deals workgroups to
+    // the eight XCDs round-robin by id.  With xcd_rows set, workgroup b runs
+    // turn j = b / 8 on XCD b % 8, and the turns of one XCD walk whole rows
+    // (row = 8 (j / tiles_per_row) + b % 8): all segments of a row share one
+    // L2, so the cache lines that x-shifted pulls share between neighbouring
+    // segments are fetched from HBM once, while the eight XCDs together still
+    // sweep one compact band of rows.  Without it (few rows), segments go
+    // out in plain launch order.
+    const int wave = (int)(threadIdx.x >> 6);
+    int seg, row;
+    if (a.xcd_rows) {
+        const int b = (int)blockIdx.x;
+        const int j = b >> 3;
+        row = (j / a.tiles_per_row) * 8 + (b & 7);
+        seg = (j % a.tiles_per_row) * 4 + wave;
+        if (row >= a.rows || seg >= a.segs) return false;
+    } else {
+        const int item = (int)blockIdx.x * 4 + wave;
+        if (item >= a.items) return false;
+        seg = item % a.segs;
+        row = item / a.segs;
+    }
+    seg = __builtin_amdgcn_readfirstlane(seg);
+    row = __builtin_amdgcn_readfirstlane(row);
     const int y = row % a.ny;
     const int z = row / a.ny;
     const int xr = seg * L + lane_cell;
@@ -607,15 +638,21 @@ hipError_t step_impl(bool split, const StepArgs& a0, hipStream_t s) {
     StepArgs a = a0;
     const int L = split ? 32 : 64;  // cells per wave
     a.segs = (a.nx + L - 1) / L;
-    a.items = a.segs * a.ny * a.nz;
-    a.tiles = (a.items + 3) / 4;  // four waves per workgroup
-    a.tiles_per_xcd = (a.tiles + 7) / 8;
-    const int grid = a.tiles_per_xcd * 8;
+    a.rows = a.ny * a.nz;
+    a.items = a.segs * a.rows;
+    a.tiles_per_row = (a.segs + 3) / 4;  // four waves (segments) per workgroup
+    // whole rows per XCD once there are enough rows to keep all eight busy
+    a.xcd_rows = a.rows >= 64 ? 1 : 0;
+    const int grid = a.xcd_rows ? 8 * a.tiles_per_row * ((a.rows + 7) / 8) : (a.items + 3) / 4;
+    // Occupancy hint for the split D3Q107 FP32 kernel: asking for at least
+    // two waves per SIMD gave 4% more bandwidth than the compiler's own
+    // choice (three waves at 162 VGPRs); the other kernels run best as
+    // compiled.
+    constexpr int kSplitWaves = (D == 3 && sizeof(T) == 4) ? 2 : 1;
     if (split)
-        hipLaunchKernelGGL((k_step_split<D, T, DEV, 1>), dim3(grid), dim3(256), 0, s, a);
+        return launch_kernel(&k_step_split<D, T, DEV, kSplitWaves>, dim3(grid), dim3(256), s, a);
     else
-        hipLaunchKernelGGL((k_step<D, T, DEV, 1>), dim3(grid), dim3(256), 0, s, a);
-    return hipGetLastError();
+        return launch_kernel(&k_step<D, T, DEV, 1>, dim3(grid), dim3(256), s, a);
 }
 
 }  // namespace
@@ -628,14 +665,13 @@ hipError_t launch_init(int dim, int precision, void* dst, const double* rho,
     const int grid = (int)((N + 255) / 256);
     char* d = static_cast<char*>(dst);
     if (dim == 2 && precision == LBM_FP64)
-        hipLaunchKernelGGL((k_init<2, double, false>), dim3(grid), dim3(256), 0, s, d, rho, u, T, N, half_delta, r, wg);
+        return launch_kernel(&k_init<2, double, false>, dim3(grid), dim3(256), s, d, rho, u, T, N, half_delta, r, wg);
     else if (dim == 2)
-        hipLaunchKernelGGL((k_init<2, float, true>), dim3(grid), dim3(256), 0, s, d, rho, u, T, N, half_delta, r, wg);
+        return launch_kernel(&k_init<2, float, true>, dim3(grid), dim3(256), s, d, rho, u, T, N, half_delta, r, wg);
     else if (precision == LBM_FP64)
-        hipLaunchKernelGGL((k_init<3, double, false>), dim3(grid), dim3(256), 0, s, d, rho, u, T, N, half_delta, r, wg);
+        return launch_kernel(&k_init<3, double, false>, dim3(grid), dim3(256), s, d, rho, u, T, N, half_delta, r, wg);
     else
-        hipLaunchKernelGGL((k_init<3, float, true>), dim3(grid), dim3(256), 0, s, d, rho, u, T, N, half_delta, r, wg);
-    return hipGetLastError();
+        return launch_kernel(&k_init<3, float, true>, dim3(grid), dim3(256), s, d, rho, u, T, N, half_delta, r, wg);
 }
 
 hipError_t launch_step(int dim, int precision, bool split, const StepArgs& a, hipStream_t s) {
@@ -649,23 +685,21 @@ int step_block_cells(int, int, bool split) { return split ? 128 : 256; }
 
 hipError_t launch_readout(int dim, int precision, const ReadArgs& a, int blocks, hipStream_t s) {
     if (dim == 2 && precision == LBM_FP64)
-        hipLaunchKernelGGL((k_readout<2, double, false>), dim3(blocks), dim3(kReadBlock), 0, s, a);
+        return launch_kernel(&k_readout<2, double, false>, dim3(blocks), dim3(kReadBlock), s, a);
     else if (dim == 2)
-        hipLaunchKernelGGL((k_readout<2, float, true>), dim3(blocks), dim3(kReadBlock), 0, s, a);
+        return launch_kernel(&k_readout<2, float, true>, dim3(blocks), dim3(kReadBlock), s, a);
     else if (precision == LBM_FP64)
-        hipLaunchKernelGGL((k_readout<3, double, false>), dim3(blocks), dim3(kReadBlock), 0, s, a);
+        return launch_kernel(&k_readout<3, double, false>, dim3(blocks), dim3(kReadBlock), s, a);
     else
-        hipLaunchKernelGGL((k_readout<3, float, true>), dim3(blocks), dim3(kReadBlock), 0, s, a);
-    return hipGetLastError();
+        return launch_kernel(&k_readout<3, float, true>, dim3(blocks), dim3(kReadBlock), s, a);
 }
 
 hipError_t launch_final_reduce(int dim, const double* partials, int blocks, double* out,
                                hipStream_t s) {
     if (dim == 2)
-        hipLaunchKernelGGL((k_final_reduce<4>), dim3(1), dim3(256), 0, s, partials, blocks, out);
+        return launch_kernel(&k_final_reduce<4>, dim3(1), dim3(256), s, partials, blocks, out);
     else
-        hipLaunchKernelGGL((k_final_reduce<5>), dim3(1), dim3(256), 0, s, partials, blocks, out);
-    return hipGetLastError();
+        return launch_kernel(&k_final_reduce<5>, dim3(1), dim3(256), s, partials, blocks, out);
 }
 
 }  // namespace lbm

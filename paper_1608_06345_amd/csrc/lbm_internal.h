@@ -38,9 +38,10 @@ struct StepArgs {
     uint32_t open_end;    // bit k: axis k is zero-gradient, else periodic
     int32_t stream;       // 1: pull-stream then collide; 0: collide in place
     int32_t segs;         // row segments per row (one wave each)
+    int32_t rows;         // ny * nz
     int32_t items;        // row segments in the grid
-    int32_t tiles;        // logical workgroups (four segments each)
-    int32_t tiles_per_xcd;
+    int32_t tiles_per_row;  // workgroups (four segments each) per row
+    int32_t xcd_rows;     // 1: each XCD serves whole rows (see kernels.hip)
     double omega_f, omega_g;  // 1 / tau
     double half_delta;        // delta / 2
     double inv_dof;           // 1 / (D + delta)

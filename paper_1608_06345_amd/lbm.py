@@ -152,9 +152,10 @@ def lbm_destroy(h):
 
 
 def lbm_set_stream(h, stream):
-    """``stream``: a torch stream, a raw hipStream_t integer, or None."""
+    """``stream``: a torch stream, a raw hipStream_t integer, or None / 0 for
+    the null stream."""
     ptr = getattr(stream, "cuda_stream", stream)
-    _check(_lib.lbm_set_stream(h, ctypes.c_void_p(ptr) if ptr else None), "lbm_set_stream")
+    _check(_lib.lbm_set_stream(h, ctypes.c_void_p(ptr or 0)), "lbm_set_stream")
 
 
 def lbm_set_variant(h, variant):
