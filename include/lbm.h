@@ -52,7 +52,8 @@ enum lbm_status {
     LBM_ENOMEM = -2,     /* device allocation failed */
     LBM_EDEVICE = -3,    /* a HIP runtime call failed */
     LBM_ESTATE = -4,     /* call out of order (e.g. step before init) */
-    LBM_ENONFINITE = -5  /* a conservation total is NaN or infinite */
+    LBM_ENONFINITE = -5, /* a conservation total is NaN or infinite */
+    LBM_EBUSY = -6       /* pool: no free slot or arena space right now */
 };
 
 enum lbm_velocity_set { LBM_D2Q37 = 37, LBM_D3Q107 = 107 };
@@ -161,6 +162,94 @@ size_t lbm_footprint_bytes(int dim, int velocity_set, int precision,
  * and the scale r, derived by the library from the Gauss-Hermite moment
  * conditions.  Any output pointer may be NULL.  Returns q, or EINVAL. */
 int lbm_lattice(int velocity_set, int8_t *e, double *w, double *r);
+
+/* ------------------------------------------------------------------------
+ * Batched multi-solve pool (serving form).
+ *
+ * Many independent solves -- D2Q37 and D3Q107 grids of any size, each with
+ * its own gamma, tau_f, tau_g, boundary conditions and number of steps --
+ * stay resident in one device arena and are advanced together: every step is
+ * one launch per velocity set over all resident solves (plus one tiny
+ * counter launch), and lbm_pool_run replays K such steps from a captured
+ * hipGraph.  Membership lives in device tables, so solves can be admitted and
+ * released between replays without re-capturing (continuous batching).  Each
+ * solve follows exactly the single-solve scheme and state convention above;
+ * its arithmetic does not depend on which other solves are resident.
+ * All pool memory is owned by the pool.  A pool is not thread-safe.
+ * ---------------------------------------------------------------------- */
+typedef struct lbm_pool *lbm_pool_handle;
+
+/* One solve request.  dim 2 uses D2Q37, dim 3 uses D3Q107; gamma, tau_f,
+ * tau_g, grid and bc as in lbm_create; steps >= 0 is the number of steps the
+ * pool runs it for. */
+typedef struct {
+    int dim;
+    double gamma, tau_f, tau_g;
+    int64_t nx, ny, nz;
+    uint32_t bc;
+    int64_t steps;
+} lbm_request;
+
+typedef struct {
+    size_t budget_bytes;       /* arena size */
+    size_t used_bytes;         /* held by resident solves */
+    size_t largest_free_bytes; /* biggest request that fits now */
+    int max_slots, resident, graphs;
+} lbm_pool_info;
+
+/* Create a pool: an arena of budget_bytes of device memory, up to max_slots
+ * (1..65536) resident solves, all stored in `precision`.  EINVAL for bad
+ * arguments; ENOMEM if the arena cannot be allocated. */
+int lbm_pool_create(size_t budget_bytes, int max_slots, int precision,
+                    lbm_pool_handle *out);
+int lbm_pool_destroy(lbm_pool_handle p);
+/* Run the pool's work on `stream` (as lbm_set_stream). */
+int lbm_pool_set_stream(lbm_pool_handle p, void *stream);
+
+/* Arena bytes a request occupies (both distributions, both ping-pong
+ * sides); 0 if the request's shape is invalid.  This is the admission
+ * footprint. */
+size_t lbm_pool_request_bytes(const lbm_request *r, int precision);
+
+/* Admit a request with its initial fields (as lbm_init_fields: host
+ * arrays rho [N], u [dim][N], T [N]; the _dev form takes device arrays on the
+ * pool's stream).  On success *slot receives the slot id and the solve is at
+ * step 0.  EINVAL for an invalid request; ENOMEM if it can never fit the
+ * arena; EBUSY if no slot or no contiguous arena space is free now (retry
+ * after releasing finished solves). */
+int lbm_pool_admit(lbm_pool_handle p, const lbm_request *r, const double *rho,
+                   const double *u, const double *T, int *slot);
+int lbm_pool_admit_dev(lbm_pool_handle p, const lbm_request *r,
+                       const double *rho, const double *u, const double *T,
+                       int *slot);
+
+/* Advance every resident solve that has steps left by up to `ticks` steps
+ * (0..4096), asynchronously, as one replay of a captured graph (captured on
+ * first use for each ticks value).  lbm_pool_run_eager enqueues the same
+ * launches without a graph. */
+int lbm_pool_run(lbm_pool_handle p, int ticks);
+int lbm_pool_run_eager(lbm_pool_handle p, int ticks);
+
+/* Synchronise, then list (up to max_finished) slots that have run all their
+ * steps and were not listed before.  Their state stays resident until
+ * lbm_pool_release. */
+int lbm_pool_poll(lbm_pool_handle p, int *finished, int max_finished,
+                  int *n_finished);
+/* Steps a slot has taken so far (synchronous). */
+int lbm_pool_slot_steps(lbm_pool_handle p, int slot, int64_t *steps_done);
+
+/* Moments / totals of a slot's S_n (n = its steps done), as lbm_moments,
+ * lbm_moments_dev and lbm_totals.  EINVAL for a slot that is not resident. */
+int lbm_pool_moments(lbm_pool_handle p, int slot, double *rho, double *u,
+                     double *E);
+int lbm_pool_moments_dev(lbm_pool_handle p, int slot, double *rho, double *u,
+                         double *E);
+int lbm_pool_totals(lbm_pool_handle p, int slot, double *mass, double *mom,
+                    double *energy);
+
+/* Free a slot and its arena space (synchronises the pool's stream first). */
+int lbm_pool_release(lbm_pool_handle p, int slot);
+int lbm_pool_get_info(lbm_pool_handle p, lbm_pool_info *info);
 
 /* Static description of a status code. */
 const char *lbm_strerror(int code);

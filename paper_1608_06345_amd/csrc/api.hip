@@ -84,15 +84,7 @@ lbm::StepArgs step_args(const lbm_solver* h, const void* src, void* dst, bool st
     a.nxy = (int32_t)(h->nx * h->ny);
     a.open_end = (h->bc & 3u) | (((h->bc >> 2) & 3u) << 1) | (((h->bc >> 4) & 3u) << 2);
     a.stream = stream ? 1 : 0;
-    a.omega_f = 1.0 / h->tau_f;
-    a.omega_g = 1.0 / h->tau_g;
-    a.half_delta = 0.5 * h->delta;
-    a.inv_dof = 1.0 / (h->dim + h->delta);
-    a.r = h->lat->r;
-    for (int g = 0; g < h->lat->groups; ++g) {
-        a.w[g] = h->lat->w_group[g];
-        a.wf[g] = (float)h->lat->w_group[g];
-    }
+    a.ph = lbm::physics_of(h->dim, h->delta, h->tau_f, h->tau_g);
     return a;
 }
 
@@ -134,6 +126,7 @@ const char* lbm_strerror(int code) {
         case LBM_EDEVICE: return "HIP runtime error";
         case LBM_ESTATE: return "call out of order (no initial fields)";
         case LBM_ENONFINITE: return "non-finite conservation total";
+        case LBM_EBUSY: return "no free pool slot or arena space now";
         default: return "unknown status";
     }
 }

@@ -142,6 +142,22 @@ std::once_flag g_once;
 
 }  // namespace
 
+Physics physics_of(int dim, double delta, double tau_f, double tau_g) {
+    const LatticeTables& t = lattice_tables(dim);
+    Physics ph;
+    std::memset(&ph, 0, sizeof(ph));
+    ph.omega_f = 1.0 / tau_f;
+    ph.omega_g = 1.0 / tau_g;
+    ph.half_delta = 0.5 * delta;
+    ph.inv_dof = 1.0 / (dim + delta);
+    ph.r = t.r;
+    for (int g = 0; g < t.groups; ++g) {
+        ph.w[g] = t.w_group[g];
+        ph.wf[g] = (float)t.w_group[g];
+    }
+    return ph;
+}
+
 const LatticeTables& lattice_tables(int dim) {
     std::call_once(g_once, [] {
         derive<2>(g_tables[0]);

@@ -5,6 +5,9 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <tuple>
+#include <type_traits>
+#include <utility>
 
 #include "lbm.h"
 #include "velocity_set.h"
@@ -27,10 +30,20 @@ struct WGroups {
     double w[10];
 };
 
+// Physical parameters of one solve as the collision uses them.
+struct Physics {
+    double omega_f, omega_g;  // 1 / tau
+    double half_delta;        // delta / 2
+    double inv_dof;           // 1 / (D + delta)
+    double r;                 // lattice scale, xi = r e
+    double w[10];             // group weights
+    float wf[10];             // the same, rounded to float
+};
+
 // Arguments of the fused step kernel (passed by value in the kernarg
 // segment, so every field is wave-uniform and lives in SGPRs).
 struct StepArgs {
-    const void* src;      // [2][Q][N]: g populations, then h populations
+    const void* src;      // [Q][2][N]: per population the g plane, then the h plane
     void* dst;            // same layout
     int64_t N;            // cells
     int32_t nx, ny, nz;
@@ -42,13 +55,11 @@ struct StepArgs {
     int32_t items;        // row segments in the grid
     int32_t tiles_per_row;  // workgroups (four segments each) per row
     int32_t xcd_rows;     // 1: each XCD serves whole rows (see kernels.hip)
-    double omega_f, omega_g;  // 1 / tau
-    double half_delta;        // delta / 2
-    double inv_dof;           // 1 / (D + delta)
-    double r;
-    double w[10];             // group weights
-    float wf[10];             // the same, rounded to float
+    Physics ph;
 };
+
+// Collision parameters of a solve (lattice.cpp).
+Physics physics_of(int dim, double delta, double tau_f, double tau_g);
 
 // Arguments of the readout kernel (moments and conservation partials).
 struct ReadArgs {
@@ -64,6 +75,20 @@ struct ReadArgs {
     double* E;                // [N] or null
     double* partials;         // [blocks][D + 2] or null
 };
+
+// Launch with the launch's own status (hipLaunchKernel), so that an error
+// left behind by unrelated work in the process is not taken for ours.
+template <typename... KArgs, typename... Args>
+inline hipError_t launch_kernel(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStream_t s,
+                         Args&&... args) {
+    std::tuple<std::decay_t<KArgs>...> vals(std::forward<Args>(args)...);
+    void* ptrs[sizeof...(KArgs) > 0 ? sizeof...(KArgs) : 1];
+    std::apply([&](auto&... v) {
+        int i = 0;
+        ((ptrs[i++] = static_cast<void*>(&v)), ...);
+    }, vals);
+    return hipLaunchKernel(reinterpret_cast<const void*>(kernel), grid, block, ptrs, 0, s);
+}
 
 // Kernel launchers (kernels.hip).  `split` selects the layout in which one
 // lane holds the g populations of a cell and its partner lane (lane ^ 32)

@@ -1,0 +1,423 @@
+// Device code shared by the single-solve kernels (kernels.hip) and the
+// batched multi-solve kernels (pool.hip): memory helpers, the pull offsets,
+// the moments, the 4th-order equilibrium, the BGK relaxation, and the whole
+// per-cell collision in the two register layouts.
+#pragma once
+
+#include <type_traits>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+namespace core {
+
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T load_at(const char* base, uint32_t byte_off) {
+    return *reinterpret_cast<const T*>(base + byte_off);
+}
+
+// Populations are written once per step and read back only in the next
+// launch, far beyond what L2 holds: stream them out non-temporally so they do
+// not evict the lines that neighbouring waves are still pulling from.
+template <typename T>
+__device__ __forceinline__ void store_at(char* base, uint32_t byte_off, T v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<T*>(base + byte_off));
+}
+
+// Source coordinate of a pull along one axis: x - e, wrapped (periodic) or
+// clamped (zero gradient).
+__device__ __forceinline__ int pull_coord(int x, int e, int n, bool open_end) {
+    int s = x - e;
+    if (open_end) return s < 0 ? 0 : (s > n - 1 ? n - 1 : s);
+    if (n >= 3) return s < 0 ? s + n : (s >= n ? s - n : s);
+    s %= n;
+    return s < 0 ? s + n : s;
+}
+
+// Per-axis source offsets (in cells) for shifts e = -3..3, index e + 3.
+template <int D>
+struct PullTable {
+    int x[7], y[7], z[7];
+    __device__ __forceinline__ void fill(int cx, int cy, int cz, int nx, int ny,
+                                         int nz, int nxy, uint32_t open_end,
+                                         bool stream) {
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            const int e = stream ? k - 3 : 0;
+            x[k] = pull_coord(cx, e, nx, open_end & 1u);
+            y[k] = pull_coord(cy, e, ny, open_end & 2u) * nx;
+            if constexpr (D == 3) z[k] = pull_coord(cz, e, nz, open_end & 4u) * nxy;
+        }
+    }
+    // source cell of the population with lattice vector (EX, EY, EZ)
+    template <int EX, int EY, int EZ>
+    __device__ __forceinline__ int src() const {
+        if constexpr (D == 3) return x[EX + 3] + y[EY + 3] + z[EZ + 3];
+        else return x[EX + 3] + y[EY + 3];
+    }
+};
+
+
+// Cell -> (x, y, z).
+__device__ __forceinline__ void coords(int cell, int nx, int nxy, int& x, int& y,
+                                       int& z) {
+    z = cell / nxy;
+    const int rem = cell - z * nxy;
+    y = rem / nx;
+    x = rem - y * nx;
+}
+
+// The 4th-order equilibrium of one cell, as a polynomial in c = xi . u per
+// shell |xi|^2 = q (one shell per group):
+//   P(c) = A0 + A1 c + A2 c^2 + c^3/6 + c^4/24,
+//   A0 - 1 = (-U + t(q-D))/2 + (3U^2 + 6t(D+2-q)U + 3t^2(q^2-2(D+2)q+D(D+2)))/24
+//   A1 = 1 - U/2 + t(q-D-2)/2,  A2 = 1/2 - U/4 + t(q-D-4)/4,
+// U = |u|^2, t = T - 1, and F_i = w_i rho P(c_i).  The coefficients are
+// formed per group at the point of use, which keeps register live ranges
+// short.  In deviation storage (DEV) A0 is returned as A0 - 1, so that the
+// rest-state part w_i is never formed in float:
+//   F_i - w_i = w_i (rho (P_i - 1) + (rho - 1)).
+template <int D, typename T, bool DEV>
+struct Equilibrium {
+    T U, t, r2, ru[3];
+
+    __device__ __forceinline__ void setup(const T* u, T t_, T r) {
+        U = D == 3 ? u[0] * u[0] + u[1] * u[1] + u[2] * u[2] : u[0] * u[0] + u[1] * u[1];
+        t = t_;
+        r2 = r * r;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) ru[k] = k < D ? r * u[k] : T(0);
+    }
+
+    template <int QN>
+    __device__ __forceinline__ void coef(T& A0, T& A1, T& A2) const {
+        const T q = r2 * T(QN);
+        constexpr T Dd = T(D);
+        const T a0m1 = T(0.5) * (t * (q - Dd) - U) +
+                       T(1.0 / 24.0) * (T(3) * U * U + T(6) * t * (Dd + T(2) - q) * U +
+                                        T(3) * t * t * (q * q - T(2) * (Dd + T(2)) * q +
+                                                        Dd * (Dd + T(2))));
+        A0 = DEV ? a0m1 : T(1) + a0m1;
+        A1 = T(1) - T(0.5) * U + T(0.5) * t * (q - Dd - T(2));
+        A2 = T(0.5) - T(0.25) * U + T(0.25) * t * (q - Dd - T(4));
+    }
+
+    // c = xi_i . u for the lattice vector V
+    template <int EX, int EY, int EZ>
+    __device__ __forceinline__ T dot() const {
+        T c = T(0);
+        if constexpr (EX != 0) c += T(EX) * ru[0];
+        if constexpr (EY != 0) c += T(EY) * ru[1];
+        if constexpr (D == 3 && EZ != 0) c += T(EZ) * ru[2];
+        return c;
+    }
+};
+
+// First velocity index of group g (velocities are ordered group by group).
+template <int D>
+constexpr int group_start(int g) {
+    int s = 0;
+    for (int k = 0; k < g; ++k) s += kVelSet<D>.count[k];
+    return s;
+}
+
+// Group weight in the arithmetic type (the parameters carry both).
+template <typename T>
+__device__ __forceinline__ T weight(const Physics& ph, int g);
+template <>
+__device__ __forceinline__ double weight<double>(const Physics& ph, int g) { return ph.w[g]; }
+template <>
+__device__ __forceinline__ float weight<float>(const Physics& ph, int g) { return ph.wf[g]; }
+
+// Moment sums over one set of Q populations p (scaled lattice units):
+// s0 = sum p, sj = sum e p, se = sum |e|^2 p.
+template <int D, typename T>
+__device__ __forceinline__ void moment_sums(const T* p, T& s0, T* sj, T& se) {
+    constexpr VelSet<D> V = kVelSet<D>;
+    constexpr int Q = VelSet<D>::Q;
+    T a0 = 0, ax = 0, ay = 0, az = 0, ae = 0;
+    static_for<0, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr Vel v = V.v[i];
+        const T x = p[i];
+        a0 += x;
+        if constexpr (v.x != 0) ax += T(v.x) * x;
+        if constexpr (v.y != 0) ay += T(v.y) * x;
+        if constexpr (D == 3 && v.z != 0) az += T(v.z) * x;
+        if constexpr (V.qn[v.group] != 0) ae += T(V.qn[v.group]) * x;
+    });
+    s0 = a0;
+    sj[0] = ax;
+    sj[1] = ay;
+    if constexpr (D == 3) sj[2] = az;
+    se = ae;
+}
+
+// Relax one set of populations toward their BGK targets with rate omega:
+//   t_i = w_i (alpha rho P~(c_i) + beta),
+// i.e. t_i = F_i for g (alpha = 1) and t_i = (delta/2) T F_i for h
+// (alpha = (delta/2) T); in deviation storage beta carries the rest-state
+// shift: beta = rho - 1 for g and (delta/2)(T (rho - 1) + T - 1) for h, and
+// then t_i is the target minus its rest value.
+//
+// Deviation storage (DEV) also makes the targets' discrete moments exact.
+// The weights, rounded to float, miss the quadrature identities by ~3e-8
+// relative, which would bias mass, momentum and energy by the same order in
+// every collision, always with the same sign.  In exact arithmetic
+// sum t_i = want_m, sum e_i t_i = want_j and sum |e_i|^2 t_i = want_e hold
+// already; here the float residuals of those sums are folded back into the
+// rest population and the 2D axis populations (group |e| = 1):
+//   mass     into the rest population,
+//   momentum +d/2 and -d/2 into the +e_k / -e_k pair (no mass, no energy),
+//   energy   +d/(2D) into each axis population, -d into the rest (no mass,
+//            no momentum).
+// je_on = 0 restricts the correction to the mass (used for h, whose only
+// conserved moment is its sum).
+template <int D, typename T, bool DEV>
+__device__ __forceinline__ void relax(T* p, const Equilibrium<D, T, DEV>& eq,
+                                      const Physics& a, T arho, T beta, T omega, T want_m,
+                                      const T* want_j, T want_e, T je_on) {
+    constexpr VelSet<D> V = kVelSet<D>;
+    constexpr int G = VelSet<D>::G;
+    static_assert(V.v[1].group == 1 && V.v[2 * D].group == 1 && V.v[2 * D + 1].group == 2,
+                  "the axis populations must follow the rest population");
+    T sm = 0, sjx = 0, sjy = 0, sjz = 0, se = 0;
+    T t1[2 * D];  // targets of the axis populations, corrected below
+    static_for<1, G>([&](auto Gi) {
+        constexpr int g = decltype(Gi)::value;
+        T A0, A1, A2;
+        eq.template coef<V.qn[g]>(A0, A1, A2);
+        const T w = weight<T>(a, g);
+        constexpr int first = group_start<D>(g);
+        static_for<0, V.count[g] / 2>([&](auto Pi) {
+            constexpr int i = first + 2 * decltype(Pi)::value;
+            constexpr Vel v = V.v[i];
+            const T c = eq.template dot<v.x, v.y, v.z>();
+            const T c2 = c * c;
+            const T even = A0 + c2 * (A2 + c2 * T(1.0 / 24.0));
+            const T odd = c * (A1 + c2 * T(1.0 / 6.0));
+            const T tp = w * (arho * (even + odd) + beta);
+            const T tm = w * (arho * (even - odd) + beta);
+            if constexpr (DEV) {
+                const T sum = tp + tm;
+                const T dif = tp - tm;
+                sm += sum;
+                if constexpr (v.x != 0) sjx += T(v.x) * dif;
+                if constexpr (v.y != 0) sjy += T(v.y) * dif;
+                if constexpr (D == 3 && v.z != 0) sjz += T(v.z) * dif;
+                se += T(V.qn[g]) * sum;
+            }
+            if constexpr (DEV && g == 1) {
+                t1[i - 1] = tp;
+                t1[i] = tm;
+            } else {
+                p[i] = p[i] + omega * (tp - p[i]);
+                p[i + 1] = p[i + 1] + omega * (tm - p[i + 1]);
+            }
+        });
+    });
+    T A0, A1, A2;
+    eq.template coef<0>(A0, A1, A2);
+    T t0 = weight<T>(a, 0) * (arho * A0 + beta);
+    if constexpr (DEV) {
+        sm += t0;
+        const T dm = want_m - sm;
+        const T de = je_on * (want_e - se);
+        const T dj[3] = {je_on * (want_j[0] - sjx), je_on * (want_j[1] - sjy),
+                         D == 3 ? je_on * (want_j[2] - sjz) : T(0)};
+        t0 += dm - de;
+        const T de_axis = de * T(1.0 / (2 * D));
+        static_for<0, D>([&](auto I) {
+            constexpr int k = decltype(I)::value;
+            constexpr Vel v = V.v[1 + 2 * k];  // +e_axis (first of its pair)
+            constexpr int axis = v.x != 0 ? 0 : (v.y != 0 ? 1 : 2);
+            const T half = T(0.5) * dj[axis];
+            const T tp = t1[2 * k] + de_axis + half;
+            const T tm = t1[2 * k + 1] + de_axis - half;
+            p[1 + 2 * k] = p[1 + 2 * k] + omega * (tp - p[1 + 2 * k]);
+            p[2 + 2 * k] = p[2 + 2 * k] + omega * (tm - p[2 + 2 * k]);
+        });
+    }
+    p[0] = p[0] + omega * (t0 - p[0]);
+}
+
+// Macroscopic state of a cell from the moment sums.
+template <int D, typename T, bool DEV>
+__device__ __forceinline__ void macro(T s0, const T* sj, T se, T sh, T r,
+                                      double inv_dof, double half_delta, T& rho,
+                                      T& drho, T* u, T& t) {
+    const T r2 = r * r;
+    if constexpr (DEV) {
+        drho = s0;
+        rho = T(1) + drho;
+    } else {
+        rho = s0;
+        drho = s0 - T(1);
+    }
+    const T inv_rho = T(1) / rho;
+#pragma unroll
+    for (int k = 0; k < D; ++k) u[k] = r * sj[k] * inv_rho;
+    const T U = D == 3 ? u[0] * u[0] + u[1] * u[1] + u[2] * u[2]
+                       : u[0] * u[0] + u[1] * u[1];
+    const T X = T(0.5) * r2 * se + sh;  // sum xi^2 g/2 + sum h (deviations in DEV)
+    if constexpr (DEV) {
+        // t = T - 1 = (2 (X - drho (D+delta)/2) / rho - U) / (D+delta): no
+        // cancellation against the rest energy in float
+        const T half_dof = T(0.5 * double(D)) + T(half_delta);
+        t = (T(2) * (X - drho * half_dof) * inv_rho - U) * T(inv_dof);
+    } else {
+        t = (T(2) * X * inv_rho - U) * T(inv_dof) - T(1);
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// Pull offsets of one wave's row segment.  y, z and every pull offset along
+// them are wave-uniform (scalar registers); per lane only the seven x offsets
+// (shifts -3..3, wrapped or clamped) are held.  A population load is then one
+// scalar base plus one of those seven lane offsets.
+template <typename T>
+struct RowOffsets {
+    uint32_t xo[7];  // per lane
+    uint32_t yo[7];  // wave-uniform
+    uint32_t zo[7];  // wave-uniform
+    uint32_t own;    // per lane: byte offset of the lane's own cell in its row
+    uint32_t row;    // wave-uniform: byte offset of the row start
+};
+
+// Fill the offsets for the lane's cell x of row (y, z); `stream` = false
+// points every pull at the cell itself (collision without streaming).
+template <int D, typename T>
+__device__ __forceinline__ void fill_row_offsets(RowOffsets<T>& o, int x, int y, int z, int nx,
+                                                 int ny, int nz, int nxy, uint32_t open_end,
+                                                 bool stream, uint32_t role_off) {
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        const int e = stream ? k - 3 : 0;
+        o.xo[k] = (uint32_t)pull_coord(x, e, nx, open_end & 1u) * (uint32_t)sizeof(T) + role_off;
+        o.yo[k] = (uint32_t)(pull_coord(y, e, ny, open_end & 2u) * nx) * (uint32_t)sizeof(T);
+        if constexpr (D == 3)
+            o.zo[k] = (uint32_t)(pull_coord(z, e, nz, open_end & 4u) * nxy) * (uint32_t)sizeof(T);
+        else
+            o.zo[k] = 0;
+    }
+    o.own = (uint32_t)x * (uint32_t)sizeof(T) + role_off;
+    o.row = (uint32_t)(y * nx + z * nxy) * (uint32_t)sizeof(T);
+}
+
+// Collision of one cell, one lane holding all 2Q populations (g and h).
+template <int D, typename T, bool DEV>
+__device__ __forceinline__ void collide_lane(T* g, T* h, const Physics& ph) {
+    T s0, sj[3] = {0, 0, 0}, se, sh, dummy_j[3], dummy_e;
+    moment_sums<D, T>(g, s0, sj, se);
+    moment_sums<D, T>(h, sh, dummy_j, dummy_e);
+    T rho, drho, u[3] = {0, 0, 0}, t;
+    macro<D, T, DEV>(s0, sj, se, sh, T(ph.r), ph.inv_dof, ph.half_delta, rho, drho, u, t);
+    Equilibrium<D, T, DEV> eq;
+    eq.setup(u, t, T(ph.r));
+    const T hd = T(ph.half_delta);
+    const T hdT = hd * (T(1) + t);
+    // BGK targets: F for g; (delta/2) T F for h (shifted by the rest state in
+    // deviation storage); exact target moments for the correction
+    const T beta_g = DEV ? drho : T(0);
+    const T beta_h = DEV ? hdT * drho + hd * t : T(0);
+    const T want_e = (rho * eq.U + T(D) * (drho + rho * t)) / eq.r2;
+    relax<D, T, DEV>(g, eq, ph, rho, beta_g, T(ph.omega_f), drho, sj, want_e, T(1));
+    relax<D, T, DEV>(h, eq, ph, hdT * rho, beta_h, T(ph.omega_g), hd * (drho + rho * t), sj,
+                     T(0), T(0));
+}
+
+// Collision of one cell in the split layout: lane l < 32 holds the g
+// populations of its cell, lane l + 32 the h populations of the same cell
+// (role 1).  The moment sums are exchanged between the halves (lane ^ 32);
+// both halves evaluate the same equilibrium, each relaxes its own
+// distribution.  Every lane of the wave must take part (the exchange).
+template <int D, typename T, bool DEV>
+__device__ __forceinline__ void collide_split(T* p, int role, const Physics& ph) {
+    T s0, sj[3] = {0, 0, 0}, se;
+    moment_sums<D, T>(p, s0, sj, se);
+    const T o0 = __shfl_xor(s0, 32);
+    T oj[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < D; ++k) oj[k] = __shfl_xor(sj[k], 32);
+    const T oe = __shfl_xor(se, 32);
+    const T g0 = role ? o0 : s0;
+    T gj[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < D; ++k) gj[k] = role ? oj[k] : sj[k];
+    const T ge = role ? oe : se;
+    const T sh = role ? s0 : o0;
+
+    T rho, drho, u[3] = {0, 0, 0}, t;
+    macro<D, T, DEV>(g0, gj, ge, sh, T(ph.r), ph.inv_dof, ph.half_delta, rho, drho, u, t);
+    Equilibrium<D, T, DEV> eq;
+    eq.setup(u, t, T(ph.r));
+    const T hd = T(ph.half_delta);
+    const T hdT = hd * (T(1) + t);
+    const T arho = role ? hdT * rho : rho;
+    const T beta = DEV ? (role ? hdT * drho + hd * t : drho) : T(0);
+    const T want_e = (rho * eq.U + T(D) * (drho + rho * t)) / eq.r2;
+    const T want_m = role ? hd * (drho + rho * t) : drho;
+    relax<D, T, DEV>(p, eq, ph, arho, beta, role ? T(ph.omega_g) : T(ph.omega_f), want_m, gj,
+                     want_e, role ? T(0) : T(1));
+}
+
+// Pull the lane's cell (lane layout): g and h of every population.
+template <int D, typename T>
+__device__ __forceinline__ void load_lane(const char* src, uint32_t plane, const RowOffsets<T>& o,
+                                          T* g, T* h) {
+    constexpr VelSet<D> V = kVelSet<D>;
+    static_for<0, VelSet<D>::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr Vel v = V.v[i];
+        const char* base = src + (size_t)(2 * i) * plane + o.yo[v.y + 3] + o.zo[v.z + 3];
+        g[i] = load_at<T>(base, o.xo[v.x + 3]);
+        h[i] = load_at<T>(base + plane, o.xo[v.x + 3]);
+    });
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void store_lane(char* dst, uint32_t plane, const RowOffsets<T>& o,
+                                           const T* g, const T* h) {
+    char* row = dst + o.row;
+    static_for<0, VelSet<D>::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        char* base = row + (size_t)(2 * i) * plane;
+        store_at<T>(base, o.own, g[i]);
+        store_at<T>(base + plane, o.own, h[i]);
+    });
+}
+
+// Pull the lane's half of its cell (split layout; the role offset is in o).
+template <int D, typename T>
+__device__ __forceinline__ void load_split(const char* src, uint32_t plane,
+                                           const RowOffsets<T>& o, T* p) {
+    constexpr VelSet<D> V = kVelSet<D>;
+    static_for<0, VelSet<D>::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr Vel v = V.v[i];
+        const char* base = src + (size_t)(2 * i) * plane + o.yo[v.y + 3] + o.zo[v.z + 3];
+        p[i] = load_at<T>(base, o.xo[v.x + 3]);
+    });
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void store_split(char* dst, uint32_t plane, const RowOffsets<T>& o,
+                                            const T* p) {
+    char* row = dst + o.row;
+    static_for<0, VelSet<D>::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        store_at<T>(row + (size_t)(2 * i) * plane, o.own, p[i]);
+    });
+}
+
+}  // namespace core
+}  // namespace lbm

@@ -24,6 +24,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ESTATE, LBM_ENONFINITE = 0, -1, -2, -3, -4, -5
+LBM_EBUSY = -6
 LBM_D2Q37, LBM_D3Q107 = 37, 107
 LBM_BC_PERIODIC, LBM_BC_ZERO_GRADIENT = 0, 1
 LBM_FP64, LBM_FP32_DEV = 0, 1
@@ -55,6 +56,18 @@ class _Info(ctypes.Structure):
                 ("steps", ctypes.c_int64), ("device_bytes", ctypes.c_size_t)]
 
 
+class lbm_request(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("gamma", ctypes.c_double), ("tau_f", ctypes.c_double),
+                ("tau_g", ctypes.c_double), ("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
+                ("nz", ctypes.c_int64), ("bc", ctypes.c_uint32), ("steps", ctypes.c_int64)]
+
+
+class _PoolInfo(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_size_t), ("used_bytes", ctypes.c_size_t),
+                ("largest_free_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int),
+                ("resident", ctypes.c_int), ("graphs", ctypes.c_int)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
@@ -78,6 +91,20 @@ def _load():
         "lbm_totals": [vp, dp, dp, dp],
         "lbm_get_info": [vp, ctypes.POINTER(_Info)],
         "lbm_lattice": [i32, ctypes.POINTER(ctypes.c_int8), dp, dp],
+        "lbm_pool_create": [ctypes.c_size_t, i32, i32, ctypes.POINTER(vp)],
+        "lbm_pool_destroy": [vp],
+        "lbm_pool_set_stream": [vp, vp],
+        "lbm_pool_admit": [vp, ctypes.POINTER(lbm_request), dp, dp, dp, ctypes.POINTER(i32)],
+        "lbm_pool_admit_dev": [vp, ctypes.POINTER(lbm_request), vp, vp, vp, ctypes.POINTER(i32)],
+        "lbm_pool_run": [vp, i32],
+        "lbm_pool_run_eager": [vp, i32],
+        "lbm_pool_poll": [vp, ctypes.POINTER(i32), i32, ctypes.POINTER(i32)],
+        "lbm_pool_slot_steps": [vp, i32, ctypes.POINTER(i64)],
+        "lbm_pool_moments": [vp, i32, dp, dp, dp],
+        "lbm_pool_moments_dev": [vp, i32, vp, vp, vp],
+        "lbm_pool_totals": [vp, i32, dp, dp, dp],
+        "lbm_pool_release": [vp, i32],
+        "lbm_pool_get_info": [vp, ctypes.POINTER(_PoolInfo)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -85,6 +112,8 @@ def _load():
         f.restype = ctypes.c_int
     lib.lbm_footprint_bytes.argtypes = [i32, i32, i32, i64, i64, i64]
     lib.lbm_footprint_bytes.restype = ctypes.c_size_t
+    lib.lbm_pool_request_bytes.argtypes = [ctypes.POINTER(lbm_request), i32]
+    lib.lbm_pool_request_bytes.restype = ctypes.c_size_t
     lib.lbm_strerror.argtypes = [i32]
     lib.lbm_strerror.restype = ctypes.c_char_p
     return lib
@@ -290,3 +319,133 @@ class Solver:
 
     def set_variant(self, variant):
         lbm_set_variant(self.h, variant)
+
+
+# --------------------------------------------------------------------------
+# Batched multi-solve pool
+
+
+def make_request(dim, gamma, tau_f, tau_g, nx, ny, nz=1, bc=0, steps=0):
+    return lbm_request(dim, gamma, tau_f, tau_g, nx, ny, nz if dim == 3 else 1, bc, steps)
+
+
+def lbm_pool_request_bytes(req, precision):
+    return int(_lib.lbm_pool_request_bytes(ctypes.byref(req), precision))
+
+
+def lbm_pool_create(budget_bytes, max_slots, precision):
+    p = ctypes.c_void_p()
+    _check(_lib.lbm_pool_create(int(budget_bytes), int(max_slots), int(precision),
+                                ctypes.byref(p)), "lbm_pool_create")
+    return p
+
+
+def lbm_pool_create_rc(budget_bytes, max_slots, precision):
+    p = ctypes.c_void_p()
+    rc = _lib.lbm_pool_create(int(budget_bytes), int(max_slots), int(precision),
+                              ctypes.byref(p))
+    if rc == LBM_OK:
+        _lib.lbm_pool_destroy(p)
+    return rc
+
+
+def lbm_pool_destroy(p):
+    _check(_lib.lbm_pool_destroy(p), "lbm_pool_destroy")
+
+
+class Pool:
+    """A batched multi-solve pool (see lbm.h).  ``admit`` returns the slot,
+    or None when the pool has no room right now (EBUSY)."""
+
+    def __init__(self, budget_bytes, max_slots, precision=LBM_FP32_DEV):
+        self.p = lbm_pool_create(budget_bytes, max_slots, precision)
+        self.precision = precision
+        self.requests = {}
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def close(self):
+        if self.p is not None:
+            lbm_pool_destroy(self.p)
+            self.p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        ptr = getattr(stream, "cuda_stream", stream)
+        _check(_lib.lbm_pool_set_stream(self.p, ctypes.c_void_p(ptr or 0)), "lbm_pool_set_stream")
+
+    def admit(self, req, rho, u, T):
+        n = req.nx * req.ny * req.nz
+        rho, u, T = _host(rho, n), _host(u, req.dim * n), _host(T, n)
+        slot = ctypes.c_int(-1)
+        rc = _lib.lbm_pool_admit(self.p, ctypes.byref(req), _dp(rho), _dp(u), _dp(T),
+                                 ctypes.byref(slot))
+        if rc == LBM_EBUSY:
+            return None
+        _check(rc, "lbm_pool_admit")
+        self.requests[slot.value] = req
+        return slot.value
+
+    def admit_dev(self, req, rho, u, T):
+        n = req.nx * req.ny * req.nz
+        slot = ctypes.c_int(-1)
+        rc = _lib.lbm_pool_admit_dev(self.p, ctypes.byref(req), _dev_ptr(rho, n),
+                                     _dev_ptr(u, req.dim * n), _dev_ptr(T, n),
+                                     ctypes.byref(slot))
+        if rc == LBM_EBUSY:
+            return None
+        _check(rc, "lbm_pool_admit_dev")
+        self.requests[slot.value] = req
+        return slot.value
+
+    def run(self, ticks):
+        _check(_lib.lbm_pool_run(self.p, int(ticks)), "lbm_pool_run")
+
+    def run_eager(self, ticks):
+        _check(_lib.lbm_pool_run_eager(self.p, int(ticks)), "lbm_pool_run_eager")
+
+    def poll(self, max_finished=1024):
+        buf = (ctypes.c_int * max_finished)()
+        n = ctypes.c_int(0)
+        _check(_lib.lbm_pool_poll(self.p, buf, max_finished, ctypes.byref(n)), "lbm_pool_poll")
+        return [buf[i] for i in range(n.value)]
+
+    def steps_done(self, slot):
+        v = ctypes.c_int64(0)
+        _check(_lib.lbm_pool_slot_steps(self.p, slot, ctypes.byref(v)), "lbm_pool_slot_steps")
+        return v.value
+
+    def moments(self, slot):
+        req = self.requests[slot]
+        n = req.nx * req.ny * req.nz
+        rho, u, E = np.empty(n), np.empty((req.dim, n)), np.empty(n)
+        _check(_lib.lbm_pool_moments(self.p, slot, _dp(rho), _dp(u), _dp(E)), "lbm_pool_moments")
+        return rho, u, E
+
+    def totals(self, slot):
+        req = self.requests[slot]
+        mass, energy, mom = np.zeros(1), np.zeros(1), np.zeros(3)
+        rc = _lib.lbm_pool_totals(self.p, slot, _dp(mass), _dp(mom), _dp(energy))
+        out = (float(mass[0]), mom[:req.dim].copy(), float(energy[0]))
+        if rc == LBM_ENONFINITE:
+            raise NonFiniteError(rc, "lbm_pool_totals", out)
+        _check(rc, "lbm_pool_totals")
+        return out
+
+    def release(self, slot):
+        _check(_lib.lbm_pool_release(self.p, slot), "lbm_pool_release")
+        self.requests.pop(slot, None)
+
+    def info(self):
+        inf = _PoolInfo()
+        _check(_lib.lbm_pool_get_info(self.p, ctypes.byref(inf)), "lbm_pool_get_info")
+        return {name: getattr(inf, name) for name, _ in _PoolInfo._fields_}
