@@ -23,6 +23,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -121,6 +123,52 @@ def run_path(name, p, steps, warmup):
     }
 
 
+def serving_runs(measured_gbs, n_requests):
+    """The batched serving form.
+
+    tube_ensemble: 512 quasi-1D shock tubes (D2Q37, Nx log-uniform in
+      [100, 4000], Ny 4, gamma uniform in [1.1, 1.67], pressure ratio
+      log-uniform in [2, 20], density ratio uniform in [2, 10]), FP32, 1000
+      steps each, all resident in one pool and advanced by a single replay of
+      one captured 1000-step graph.
+    poisson_trace: the mixed request stream (50% 2D 256^2..2048^2, 30% 3D
+      64^3..192^3, 20% tubes; gamma in [1.1, 1.67]; 200..2000 steps) arriving
+      at 80% of the batched capacity estimated from the bandwidth just
+      measured, served (a) by continuous batching in an FP32 pool with 8-step
+      graph replays and (b) one request at a time in FP64 with eager launches.
+    """
+    import torch
+
+    from paper_1608_06345_amd import lbm, serving
+
+    out = {}
+    tubes = serving.tube_ensemble(512, steps=1000, seed=4)
+    budget = sum(lbm.lbm_pool_request_bytes(r.req, lbm.LBM_FP32_DEV) for r in tubes) + (1 << 30)
+    tr, span = serving.serve_pool(tubes, budget, max_slots=600, ticks=1000, realtime=False)
+    out["tube_ensemble"] = dict(serving.summarize(tr, span), graph_steps=1000,
+                                workload="512 shock tubes, D2Q37 FP32, 1000 steps, one graph")
+    torch.cuda.empty_cache()
+    print(f"# tube ensemble: {out['tube_ensemble']}", file=sys.stderr, flush=True)
+
+    probe = serving.poisson_trace(400, 1.0, seed=5)
+    mean_bytes = np.mean([serving.request_bytes_moved(r) for r in probe if serving.valid(r)])
+    rate = 0.8 * measured_gbs * 1e9 / mean_bytes
+    trace = serving.poisson_trace(n_requests, rate, seed=5)
+    tr, span = serving.serve_pool(trace, 250 << 30, max_slots=256, ticks=8)
+    batched = serving.summarize(tr, span)
+    torch.cuda.empty_cache()
+    print(f"# serving, FP32 pool: {batched}", file=sys.stderr, flush=True)
+    trace = serving.poisson_trace(n_requests, rate, seed=5)
+    tr, span = serving.serve_sequential(trace, precision=lbm.LBM_FP64)
+    seq = serving.summarize(tr, span)
+    torch.cuda.empty_cache()
+    print(f"# serving, FP64 one at a time: {seq}", file=sys.stderr, flush=True)
+    out["poisson_trace"] = {"rate_per_s": round(rate, 3), "requests": n_requests,
+                            "fp32_pool_continuous_batching": batched,
+                            "fp64_single_solve_sequential": seq}
+    return out
+
+
 def cpu_baseline(p, seconds_hint=15.0):
     """The FP64 oracle, as it stands, on a bounded sample of the headline
     workload: the same lattice, parameters and field recipe on a 64^3 grid
@@ -181,6 +229,10 @@ def main():
     ap.add_argument("--path", default="d3q107_fp32", choices=sorted(PATHS))
     ap.add_argument("--no-extra", action="store_true", help="skip the other three paths")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the batched tube ensemble and the serving trace")
+    ap.add_argument("--serving-requests", type=int, default=24,
+                    help="requests in the Poisson serving trace")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy a device buffer of BYTES bytes 5 times (a plain copy "
                          "kernel of known size, to scale the HBM byte counters) and exit")
@@ -238,6 +290,8 @@ def main():
                                             "ms_per_step", "steps")}
                   for k, v in paths.items()},
     }
+    if not args.no_serving:
+        out["serving"] = serving_runs(res["gbs"], args.serving_requests)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(head)
     print(json.dumps(out), flush=True)

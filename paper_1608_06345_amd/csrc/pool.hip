@@ -14,18 +14,19 @@
 //   directory  per velocity set: the first tile of each resident solve and
 //              its slot, in ascending tile order, plus the total tile count.
 //
-// A step launch is a fixed grid that strides over all tiles of its velocity
-// set.  Each tile belongs to one solve (binary search in the directory) and
+// A step launch has one workgroup per tile of its velocity set.  Each tile
+// belongs to one solve (binary search in the directory) and
 // covers four row segments, exactly as in a single-solve launch, including
-// the whole-rows-per-XCD order (tile starts are multiples of 8, the grid size
-// is a multiple of 8, so tile t always runs on XCD t % 8).  Ping-pong parity
+// the whole-rows-per-XCD order (tile starts are multiples of 8, so tile t
+// runs on XCD t % 8 as in a single launch).  Ping-pong parity
 // comes from the solve's own counter: it reads side steps_done & 1 and
 // writes the other.  Solves that have used up their steps are skipped.
 //
 // Because the kernels read all of this from device memory, a captured graph
-// of K steps never changes: admissions and releases only rewrite the table
-// and the directory between replays (continuous batching without
-// re-capture).
+// of K steps keeps its topology for good: admissions and releases rewrite the
+// table and the directory between replays, and only the grid sizes of the
+// graph's step launches are updated in place when the tile count changes
+// (continuous batching without re-capture).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -69,7 +70,6 @@ namespace {
 
 using namespace core;
 
-constexpr int kPoolGrid = 2048;  // multiple of 8 (XCD order); strides over all tiles
 
 template <int L>
 __device__ __forceinline__ bool pool_item(const SolveEntry& e, int local, int wave, int& seg,
@@ -86,60 +86,62 @@ __device__ __forceinline__ bool pool_item(const SolveEntry& e, int local, int wa
     return item < e.items;
 }
 
+// One workgroup per tile: the grid of each launch is exactly the tile count
+// of the resident solves (a loop over tiles would keep loop state live
+// across the whole body and cost a wave per SIMD of occupancy).
 template <int D, typename T, bool DEV, bool SPLIT, int WAVES>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
 void k_pool_step(const PoolArgs pa) {
     constexpr int Q = VelSet<D>::Q;
     constexpr int L = SPLIT ? 32 : 64;
-    const int total = pa.dir->total_tiles;
+    const int tile = (int)blockIdx.x;
+    if (tile >= pa.dir->total_tiles) return;
     const int count = pa.dir->count;
     const int lane = (int)threadIdx.x & 63;
     const int wave = (int)(threadIdx.x >> 6);
     const int role = SPLIT ? lane >> 5 : 0;
-    for (int tile = (int)blockIdx.x; tile < total; tile += (int)gridDim.x) {
-        // the resident solve that owns this tile: last begin <= tile
-        int lo = 0, hi = count - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (pa.begin[mid] <= tile) lo = mid;
-            else hi = mid - 1;
-        }
-        const int s = __builtin_amdgcn_readfirstlane(pa.slot[lo]);
-        const int local = tile - pa.begin[lo];
-        const SolveEntry& e = pa.table[s];
-        const int64_t done = pa.steps_done[s];
-        if (!e.active || done >= e.steps_total || local >= e.tiles) continue;
-        int seg, row;
-        if (!pool_item<L>(e, local, wave, seg, row)) continue;
-        seg = __builtin_amdgcn_readfirstlane(seg);
-        row = __builtin_amdgcn_readfirstlane(row);
-        const int y = row % e.ny;
-        const int z = row / e.ny;
-        const int xr = seg * L + (SPLIT ? (lane & 31) : lane);
-        const int x = xr < e.nx ? xr : e.nx - 1;  // tail lanes redo the last cell
-        const uint32_t plane = (uint32_t)e.N * (uint32_t)sizeof(T);
-        RowOffsets<T> o;
-        fill_row_offsets<D, T>(o, x, y, z, e.nx, e.ny, e.nz, e.nxy, e.open_end, true,
-                               role ? plane : 0u);
-        const int par = (int)(done & 1);
-        const char* src = reinterpret_cast<const char*>(e.base + (par ? e.side_bytes : 0));
-        char* dst = reinterpret_cast<char*>(e.base + (par ? 0 : e.side_bytes));
-        Physics ph = pa.ph;
-        ph.omega_f = e.omega_f;
-        ph.omega_g = e.omega_g;
-        ph.half_delta = e.half_delta;
-        ph.inv_dof = e.inv_dof;
-        if constexpr (SPLIT) {
-            T p[Q];
-            load_split<D, T>(src, plane, o, p);
-            collide_split<D, T, DEV>(p, role, ph);
-            store_split<D, T>(dst, plane, o, p);
-        } else {
-            T g[Q], h[Q];
-            load_lane<D, T>(src, plane, o, g, h);
-            collide_lane<D, T, DEV>(g, h, ph);
-            store_lane<D, T>(dst, plane, o, g, h);
-        }
+    // the resident solve that owns this tile: last begin <= tile
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pa.begin[mid] <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    const int s = __builtin_amdgcn_readfirstlane(pa.slot[lo]);
+    const int local = tile - pa.begin[lo];
+    const SolveEntry& e = pa.table[s];
+    const int64_t done = pa.steps_done[s];
+    if (!e.active || done >= e.steps_total || local >= e.tiles) return;
+    int seg, row;
+    if (!pool_item<L>(e, local, wave, seg, row)) return;
+    seg = __builtin_amdgcn_readfirstlane(seg);
+    row = __builtin_amdgcn_readfirstlane(row);
+    const int y = row % e.ny;
+    const int z = row / e.ny;
+    const int xr = seg * L + (SPLIT ? (lane & 31) : lane);
+    const int x = xr < e.nx ? xr : e.nx - 1;  // tail lanes redo the last cell
+    const uint32_t plane = (uint32_t)e.N * (uint32_t)sizeof(T);
+    RowOffsets<T> o;
+    fill_row_offsets<D, T>(o, x, y, z, e.nx, e.ny, e.nz, e.nxy, e.open_end, true,
+                           role ? plane : 0u);
+    const int par = (int)(done & 1);
+    const char* src = reinterpret_cast<const char*>(e.base + (par ? e.side_bytes : 0));
+    char* dst = reinterpret_cast<char*>(e.base + (par ? 0 : e.side_bytes));
+    Physics ph = pa.ph;
+    ph.omega_f = e.omega_f;
+    ph.omega_g = e.omega_g;
+    ph.half_delta = e.half_delta;
+    ph.inv_dof = e.inv_dof;
+    if constexpr (SPLIT) {
+        T p[Q];
+        load_split<D, T>(src, plane, o, p);
+        collide_split<D, T, DEV>(p, role, ph);
+        store_split<D, T>(dst, plane, o, p);
+    } else {
+        T g[Q], h[Q];
+        load_lane<D, T>(src, plane, o, g, h);
+        collide_lane<D, T, DEV>(g, h, ph);
+        store_lane<D, T>(dst, plane, o, g, h);
     }
 }
 
@@ -151,14 +153,21 @@ __global__ __launch_bounds__(256) void k_advance(const SolveEntry* table, int64_
         steps_done[s] = steps_done[s] + 1;
 }
 
+// The step kernel of a velocity set, in the pool's precision: the same
+// layouts as the single-solve launches (one lane per cell for D2Q37, the g/h
+// lane-pair split for D3Q107).
 template <typename T, bool DEV>
-hipError_t launch_pool_step(int dim, const PoolArgs& a, hipStream_t s) {
-    // same layouts as the single-solve launches: one lane per cell for
-    // D2Q37, the g/h lane-pair split for D3Q107
-    if (dim == 2)
-        return launch_kernel(&k_pool_step<2, T, DEV, false, 1>, dim3(kPoolGrid), dim3(256), s, a);
+const void* pool_step_kernel(int dim) {
+    if (dim == 2) return reinterpret_cast<const void*>(&k_pool_step<2, T, DEV, false, 1>);
     constexpr int w = sizeof(T) == 4 ? 2 : 1;
-    return launch_kernel(&k_pool_step<3, T, DEV, true, w>, dim3(kPoolGrid), dim3(256), s, a);
+    return reinterpret_cast<const void*>(&k_pool_step<3, T, DEV, true, w>);
+}
+
+template <typename T, bool DEV>
+hipError_t launch_pool_step(int dim, const PoolArgs& a, int grid, hipStream_t s) {
+    if (dim == 2) return launch_kernel(&k_pool_step<2, T, DEV, false, 1>, dim3(grid), dim3(256), s, a);
+    constexpr int w = sizeof(T) == 4 ? 2 : 1;
+    return launch_kernel(&k_pool_step<3, T, DEV, true, w>, dim3(grid), dim3(256), s, a);
 }
 
 struct Slot {
@@ -218,8 +227,14 @@ struct lbm_pool {
     bool dirty = true;
     int resident[2] = {0, 0};
     hipStream_t stream = nullptr, own_stream = nullptr;
-    std::map<int, hipGraphExec_t> graphs;  // key: ticks * 4 + velocity-set mask
-    std::vector<hipGraph_t> graph_defs;
+    int tiles_total[2] = {0, 0};  // tiles of the resident solves, per velocity set
+    struct Graph {
+        hipGraph_t def = nullptr;
+        hipGraphExec_t exec = nullptr;
+        std::vector<hipGraphNode_t> step_nodes[2];  // kernel nodes per velocity set
+        int grid[2] = {0, 0};                        // their current grid size
+    };
+    std::map<int, Graph> graphs;  // key: ticks * 4 + velocity-set mask
 };
 
 namespace {
@@ -295,6 +310,7 @@ int upload(lbm_pool* p) {
         dir->count = count;
         dir->total_tiles = total;
         p->resident[d] = count;
+        p->tiles_total[d] = total;
     }
     POOL_HIP(hipMemcpyAsync(p->d_table, p->h_upload, tb, hipMemcpyHostToDevice, p->stream));
     for (int d = 0; d < 2; ++d)
@@ -323,9 +339,10 @@ int enqueue_steps(lbm_pool* p, int ticks, int mask, hipStream_t s) {
         for (int d = 0; d < 2; ++d) {
             if (!(mask & (1 << d))) continue;
             const lbm::PoolArgs a = pool_args(p, d);
+            const int grid = p->tiles_total[d] > 0 ? p->tiles_total[d] : 1;
             hipError_t e = p->precision == LBM_FP64
-                               ? lbm::launch_pool_step<double, false>(d + 2, a, s)
-                               : lbm::launch_pool_step<float, true>(d + 2, a, s);
+                               ? lbm::launch_pool_step<double, false>(d + 2, a, grid, s)
+                               : lbm::launch_pool_step<float, true>(d + 2, a, grid, s);
             POOL_HIP(e);
         }
         POOL_HIP(lbm::launch_kernel(&lbm::k_advance, dim3((p->max_slots + 255) / 256), dim3(256),
@@ -435,8 +452,10 @@ int lbm_pool_create(size_t budget_bytes, int max_slots, int precision, lbm_pool_
 int lbm_pool_destroy(lbm_pool_handle p) {
     if (!p) return LBM_OK;
     if (p->stream) (void)hipStreamSynchronize(p->stream);
-    for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
-    for (auto g : p->graph_defs) (void)hipGraphDestroy(g);
+    for (auto& kv : p->graphs) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.def) (void)hipGraphDestroy(kv.second.def);
+    }
     if (p->arena) (void)hipFree(p->arena);
     if (p->d_table) (void)hipFree(p->d_table);
     if (p->d_steps) (void)hipFree(p->d_steps);
@@ -639,10 +658,45 @@ int lbm_pool_run(lbm_pool_handle p, int ticks) {
             if (g) (void)hipGraphDestroy(g);
             return rc2 != LBM_OK ? rc2 : lbm::err_of(e != hipSuccess ? e : e_end);
         }
-        p->graph_defs.push_back(g);
-        it = p->graphs.emplace(key, exec).first;
+        lbm_pool::Graph gr;
+        gr.def = g;
+        gr.exec = exec;
+        // remember the step-kernel nodes, to resize their grids later
+        size_t n = 0;
+        POOL_HIP(hipGraphGetNodes(g, nullptr, &n));
+        std::vector<hipGraphNode_t> nodes(n);
+        POOL_HIP(hipGraphGetNodes(g, nodes.data(), &n));
+        for (int d = 0; d < 2; ++d) {
+            const void* fn = p->precision == LBM_FP64 ? lbm::pool_step_kernel<double, false>(d + 2)
+                                                      : lbm::pool_step_kernel<float, true>(d + 2);
+            for (auto node : nodes) {
+                hipGraphNodeType type;
+                POOL_HIP(hipGraphNodeGetType(node, &type));
+                if (type != hipGraphNodeTypeKernel) continue;
+                hipKernelNodeParams kp;
+                POOL_HIP(hipGraphKernelNodeGetParams(node, &kp));
+                if (kp.func == fn) gr.step_nodes[d].push_back(node);
+            }
+            gr.grid[d] = p->tiles_total[d] > 0 ? p->tiles_total[d] : 1;
+        }
+        it = p->graphs.emplace(key, gr).first;
     }
-    POOL_HIP(hipGraphLaunch(it->second, p->stream));
+    // membership changed since this graph last ran: resize its step launches
+    // in place (the topology stays, nothing is re-captured)
+    lbm_pool::Graph& gr = it->second;
+    for (int d = 0; d < 2; ++d) {
+        const int grid = p->tiles_total[d] > 0 ? p->tiles_total[d] : 1;
+        if (grid == gr.grid[d] || gr.step_nodes[d].empty()) continue;
+        POOL_HIP(hipStreamSynchronize(p->stream));  // no replay in flight
+        for (auto node : gr.step_nodes[d]) {
+            hipKernelNodeParams kp;
+            POOL_HIP(hipGraphKernelNodeGetParams(node, &kp));
+            kp.gridDim = dim3(grid);
+            POOL_HIP(hipGraphExecKernelNodeSetParams(gr.exec, node, &kp));
+        }
+        gr.grid[d] = grid;
+    }
+    POOL_HIP(hipGraphLaunch(gr.exec, p->stream));
     return LBM_OK;
 }
 

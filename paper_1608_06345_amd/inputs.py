@@ -114,3 +114,36 @@ def shear_wave_fields(dim, nx, ny, nz=1, seed=0, amp=0.05, background=0.25):
     rho += 0.2 * amp * np.cos(2 * math.pi * x + ph[2])
     T += 0.2 * amp * np.cos(2 * math.pi * x + ph[3])
     return rho, u, T
+
+
+def smooth_fields_device(dim, nx, ny, nz=1, seed=0, a_rho=0.01, a_u=0.02, a_T=0.01,
+                         nmodes=8, kmax=8, device="cuda"):
+    """The ``smooth`` recipe (same seeded draws as smooth_fields), evaluated
+    with torch on ``device``: (rho, u, T) as contiguous float64 tensors."""
+    import torch
+
+    if dim == 2:
+        nz = 1
+    shape = (nx, ny, nz)
+    ss = np.random.SeedSequence(seed)
+    rngs = [np.random.default_rng(c) for c in ss.spawn(2 + dim)]
+    axes = [torch.arange(n, dtype=torch.float64, device=device) / n for n in shape[:dim]]
+
+    def mode_sum(amp, ks, phase):
+        out = torch.zeros(tuple(reversed(shape[:dim])), dtype=torch.float64, device=device)
+        for m in range(len(amp)):
+            arg = None
+            for d in range(dim):
+                a = 2 * math.pi * float(ks[m, d]) * axes[d]
+                view = [1] * dim
+                view[dim - 1 - d] = -1
+                a = a.reshape(view)
+                arg = a if arg is None else arg + a
+            out += float(amp[m]) * torch.cos(arg + float(phase[m]))
+        return out.reshape(-1)
+
+    s_rho = mode_sum(*_modes(rngs[0], dim, nmodes, kmax))
+    s_T = mode_sum(*_modes(rngs[1], dim, nmodes, kmax))
+    u = torch.stack([mode_sum(*_modes(rngs[2 + c], dim, nmodes, kmax)) for c in range(dim)])
+    return ((1.0 + a_rho * s_rho).contiguous(), (a_u * u).contiguous(),
+            (1.0 + a_T * s_T).contiguous())

@@ -1,0 +1,170 @@
+"""The serving form on the GPU: the continuous-batching loop and the batched
+shock-tube ensemble.
+
+  * every request served by the loop (arrivals while others run, FIFO with
+    backfill, admissions and releases between graph replays) returns the
+    same bits as the same request served alone, and as the single-solve API;
+  * the tube ensemble: per-tube L1 error against the exact Riemann solution
+    at each tube's comparison step (before any wave reaches an end), and
+    GPU-vs-oracle parity for a few tubes.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1608_06345_amd import lbm, serving
+from parity_util import oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_trace(n=12, seed=9):
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0.0
+    for k in range(n):
+        t += rng.exponential(0.01)
+        kind = ("2d", "3d", "tube")[k % 3]
+        gamma = rng.uniform(1.1, 1.6 if kind == "3d" else 1.9)
+        steps = int(rng.integers(20, 61))
+        if kind == "2d":
+            side = int(rng.integers(64, 129))
+            req = lbm.make_request(2, gamma, 0.7, 0.8, side, side - 3, steps=steps)
+            out.append(serving.Request(k, t, kind, req, 1000 + k))
+        elif kind == "3d":
+            side = int(rng.integers(16, 25))
+            req = lbm.make_request(3, gamma, 0.65, 0.65, side, side + 1, side - 2, steps=steps)
+            out.append(serving.Request(k, t, kind, req, 1000 + k))
+        else:
+            nx = int(rng.integers(100, 301))
+            left, right = serving.tube_states(rng)
+            req = lbm.make_request(2, gamma, 0.8, 0.8, nx, 4, bc=serving.OPEN_X, steps=steps)
+            out.append(serving.Request(k, t, kind, req, 1000 + k, tube=(left, right)))
+    return out
+
+
+def test_serving_loop_results_equal_alone():
+    import torch
+    got = {}
+
+    def keep(r, pool, slot):
+        got[r.rid] = pool.moments(slot)
+
+    trace = _small_trace()
+    # a small arena forces waiting and backfill
+    budget = 3 * max(lbm.lbm_pool_request_bytes(r.req, lbm.LBM_FP32_DEV) for r in trace)
+    tr, span = serving.serve_pool(trace, budget, max_slots=4, ticks=7, keep=keep)
+    s = serving.summarize(tr, span)
+    assert s["completed"] == len(trace), s
+    for r in trace:
+        f = serving.device_fields(r)
+        torch.cuda.synchronize()
+        with lbm.Pool(1 << 30, 2, lbm.LBM_FP32_DEV) as pool:
+            slot = pool.admit_dev(r.req, *f)
+            while slot not in pool.poll():
+                pool.run(5)
+            alone = pool.moments(slot)
+        q = r.req
+        with lbm.Solver(q.dim, q.gamma, q.tau_f, q.tau_g, q.nx, q.ny, q.nz, bc=q.bc,
+                        precision=lbm.LBM_FP32_DEV) as sol:
+            lbm.lbm_init_fields_dev(sol.h, *f)
+            sol.step(q.steps)
+            single = sol.moments()
+        for a, b, c in zip(got[r.rid], alone, single):
+            assert np.array_equal(a, b), f"request {r.rid}: mix != alone"
+            assert np.array_equal(a, c), f"request {r.rid}: pool != single solve"
+
+
+def test_sequential_fp64_server_completes():
+    trace = _small_trace(6, seed=3)
+    tr, span = serving.serve_sequential(trace, precision=lbm.LBM_FP64)
+    s = serving.summarize(tr, span)
+    assert s["completed"] == 6 and s["p99_s"] >= s["p50_s"] > 0
+
+
+def _tube_case(r):
+    """Exact solution, comparison step (every wave still >= 10 cells from an
+    end) and whether the tube is inside the 4th-order model's range: every
+    state of the exact solution has 0.7 <= T <= 1.4 and Mach < 0.8, and no
+    wave outruns the lattice (|speed| < 3r)."""
+    from oracle.riemann import RiemannSolution
+    left, right = r.tube
+    g = r.req.gamma
+    sol = RiemannSolution(left, right, g)
+    rr = lbm.lbm_lattice(37)[2]
+    nx = r.req.nx
+    x_d = nx // 2
+    n_cmp = min(1000, int((min(x_d, nx - x_d) - 10) * rr / sol.max_speed()))
+    states = [(left[0], left[1], left[2]), (right[0], right[1], right[2]),
+              (sol.rho_star_l, sol.u_star, sol.p_star), (sol.rho_star_r, sol.u_star, sol.p_star)]
+    temps = [p / rho for rho, _, p in states]
+    mach = max(abs(u) / math.sqrt(g * p / rho) for rho, u, p in states)
+    in_range = (min(temps) >= 0.7 and max(temps) <= 1.4 and mach < 0.8
+                and sol.max_speed() < 3 * rr)
+    return sol, n_cmp, in_range
+
+
+def test_tube_ensemble_l1_against_exact_riemann():
+    from oracle.riemann import l1_errors, shock_tube_profile
+    tubes = serving.tube_ensemble(512, seed=4)
+    cases = {}
+    for r in tubes:
+        sol, n_cmp, in_range = _tube_case(r)
+        if n_cmp >= 20 and in_range:
+            r.req.steps = n_cmp
+            cases[r.rid] = (sol, n_cmp)
+    n_in = len(cases)
+    print(f"{n_in} of {len(tubes)} ensemble tubes inside the model's range")
+    assert n_in >= 10
+    got = {}
+
+    def keep(r, pool, slot):
+        got[r.rid] = pool.moments(slot)
+
+    todo = [r for r in tubes if r.rid in cases][:48]
+    budget = sum(lbm.lbm_pool_request_bytes(r.req, lbm.LBM_FP32_DEV) for r in todo) + (1 << 26)
+    serving.serve_pool(todo, budget, max_slots=64, ticks=50, realtime=False, keep=keep)
+    rr = lbm.lbm_lattice(37)[2]
+    worst = 0.0
+    for r in todo:
+        sol, n_cmp = cases[r.rid]
+        rho, u, E = got[r.rid]
+        nx = r.req.nx
+        delta = 2.0 / (r.req.gamma - 1.0) - 2
+        T = (2 * E - np.sum(u * u, axis=0)) / (2 + delta)
+        ex = shock_tube_profile(r.tube[0], r.tube[1], r.req.gamma, nx, n_cmp, rr)
+        l1 = l1_errors(rho[:nx], u[0][:nx], (rho * T)[:nx], *ex)
+        # relative to the size of each field's jump in the exact solution
+        scale = (abs(r.tube[0][0] - r.tube[1][0]), max(1e-3, abs(sol.u_star)),
+                 abs(r.tube[0][2] - r.tube[1][2]))
+        rel = [a / s for a, s in zip(l1, scale)]
+        worst = max(worst, max(rel))
+        print(f"tube {r.rid}: nx={nx} gamma={r.req.gamma:.3f} steps={n_cmp} "
+              f"L1 rho/u/p={tuple(round(v, 5) for v in l1)} rel={tuple(round(v, 4) for v in rel)}")
+        assert np.all(np.isfinite(rho[:nx]))
+        assert max(rel) < 0.06, (r.rid, rel)
+    print(f"worst relative L1 over {len(todo)} in-range tubes: {worst:.4f}")
+
+
+def test_tube_parity_with_oracle():
+    tubes = [r for r in serving.tube_ensemble(512, seed=4) if _tube_case(r)[2]][:3]
+    for r in tubes:
+        _, n_cmp, _ = _tube_case(r)
+        n = max(20, min(n_cmp, 200))
+        r.req.steps = n
+        q = r.req
+        f = [a.cpu().numpy() for a in serving.device_fields(r)]
+        with lbm.Solver(2, q.gamma, q.tau_f, q.tau_g, q.nx, q.ny, bc=q.bc,
+                        precision=lbm.LBM_FP32_DEV) as s:
+            s.init_fields(*f)
+            s.step(n)
+            rho, u, E = s.moments()
+            T = s.temperature(u, E)
+        o = oracle_run(2, q.gamma, q.tau_f, q.tau_g, (q.nx, q.ny, 1), f, n,
+                       open_end=(True, False, False))
+        e_rho = np.max(np.abs(rho - o[0]) / o[0])
+        e_u = np.max(np.abs(u - o[1]))
+        e_T = np.max(np.abs(T - o[2]) / o[2])
+        print(f"tube {r.rid} FP32 vs oracle: rho {e_rho:.2e} u(abs) {e_u:.2e} T {e_T:.2e}")
+        assert max(e_rho, e_u, e_T) < 2e-3
