@@ -2,9 +2,10 @@
 
 Headline: D3Q107, 256^3 periodic grid, smooth seeded perturbation (amplitude
 0.01 in rho and T, 0.02 in u), gamma 1.4 (delta 2), tau_f = tau_g = 0.65,
-populations in FP32 deviation storage, 500 timed steps.  The other three
-paths (D3Q107 FP64; D2Q37 4096^2 FP32 and FP64 with tau_f 0.7, tau_g 0.8)
-are measured the same way and reported under "paths".
+populations in FP32 deviation storage, 500 timed steps.  The other paths
+(D3Q107 FP64 and half-precision scaled storage; D2Q37 4096^2 in all three
+storage precisions, tau_f 0.7, tau_g 0.8) are measured the same way and
+reported under "paths".
 
 One step = one launch of the fused step kernel over the whole grid (pull,
 moments, equilibrium, BGK relaxation of g and h, store).  Inputs are resident
@@ -13,7 +14,7 @@ bracketed by device synchronisation, timed with HIP events recorded on the
 stream the kernels run on.
 
 Roofline: algorithmic bytes per cell update = 2 (read + write) x Q x 2
-(g and h) x bytes per value; achieved GB/s = those bytes x cells / average
+(g and h) x bytes per stored value (8, 4 or 2); achieved GB/s = those bytes x cells / average
 launch time; peak = 8 TB/s HBM3E.
 """
 import argparse
@@ -30,21 +31,26 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 
-PATHS = {
-    "d3q107_fp32": dict(dim=3, shape=(256, 256, 256), gamma=1.4, tf=0.65, tg=0.65, fp32=True,
-                        seed=3, steps=500),
-    "d3q107_fp64": dict(dim=3, shape=(256, 256, 256), gamma=1.4, tf=0.65, tg=0.65, fp32=False,
-                        seed=3, steps=500),
-    "d2q37_fp32": dict(dim=2, shape=(4096, 4096, 1), gamma=1.4, tf=0.7, tg=0.8, fp32=True,
-                       seed=2, steps=1000),
-    "d2q37_fp64": dict(dim=2, shape=(4096, 4096, 1), gamma=1.4, tf=0.7, tg=0.8, fp32=False,
-                       seed=2, steps=1000),
-}
+STORAGE = {"fp64": ("FP64", 8), "fp32": ("FP32 deviation storage", 4),
+           "fp16": ("FP16 scaled deviation storage", 2)}
+
+PATHS = {}
+for _store in ("fp32", "fp64", "fp16"):
+    PATHS[f"d3q107_{_store}"] = dict(dim=3, shape=(256, 256, 256), gamma=1.4, tf=0.65, tg=0.65,
+                                     store=_store, seed=3, steps=500)
+for _store in ("fp32", "fp64", "fp16"):
+    PATHS[f"d2q37_{_store}"] = dict(dim=2, shape=(4096, 4096, 1), gamma=1.4, tf=0.7, tg=0.8,
+                                    store=_store, seed=2, steps=1000)
 
 
-def bytes_per_update(dim, fp32):
+def precision_of(store):
+    from paper_1608_06345_amd import lbm
+    return {"fp64": lbm.LBM_FP64, "fp32": lbm.LBM_FP32_DEV, "fp16": lbm.LBM_FP16_SCALED}[store]
+
+
+def bytes_per_update(dim, store):
     q = 37 if dim == 2 else 107
-    return 2 * q * 2 * (4 if fp32 else 8)
+    return 2 * q * 2 * STORAGE[store][1]
 
 
 def describe(name, p):
@@ -53,12 +59,12 @@ def describe(name, p):
     delta = 2.0 / (p["gamma"] - 1.0) - p["dim"]
     return (f"D{p['dim']}Q{q} {grid} periodic, smooth seeded field (seed {p['seed']}), "
             f"gamma {p['gamma']} (delta {delta:g}), tau_f {p['tf']}, tau_g {p['tg']}, "
-            f"{'FP32 deviation storage' if p['fp32'] else 'FP64'}")
+            f"{STORAGE[p['store']][0]}")
 
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "velocity_set.h", "lbm_internal.h", "api.hip"):
+    for f in ("kernels.hip", "step_core.h", "velocity_set.h", "lbm_internal.h", "api.hip"):
         with open(os.path.join(ROOT, "paper_1608_06345_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -89,7 +95,7 @@ def run_path(name, p, steps, warmup):
 
     nx, ny, nz = p["shape"]
     cells = nx * ny * nz
-    prec = lbm.LBM_FP32_DEV if p["fp32"] else lbm.LBM_FP64
+    prec = precision_of(p["store"])
     f = smooth_fields(p["dim"], nx, ny, nz, seed=p["seed"])
     stream = torch.cuda.Stream()  # the kernels' stream; the events go on it too
     with lbm.Solver(p["dim"], p["gamma"], p["tf"], p["tg"], nx, ny, nz, precision=prec) as s:
@@ -111,7 +117,7 @@ def run_path(name, p, steps, warmup):
         mass, mom, energy = s.totals()
     ms_step = ms / steps
     mlups = cells * steps / (ms * 1e-3) / 1e6
-    bpu = bytes_per_update(p["dim"], p["fp32"])
+    bpu = bytes_per_update(p["dim"], p["store"])
     achieved = bpu * cells / (ms_step * 1e-3) / 1e9
     traffic = measured_traffic(name, cells)
     return {
@@ -195,7 +201,7 @@ def cpu_baseline(p, seconds_hint=15.0):
     cells = shape[0] * shape[1] * shape[2]
     r_o, u_o, E_o = o.moments()
     T_o = o.temperature(u_o, E_o)
-    prec = lbm.LBM_FP32_DEV if p["fp32"] else lbm.LBM_FP64
+    prec = precision_of(p["store"])
     with lbm.Solver(dim, p["gamma"], p["tf"], p["tg"], *shape, precision=prec) as s:
         s.init_fields(*f)
         s.step(steps)
@@ -227,7 +233,7 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--path", default="d3q107_fp32", choices=sorted(PATHS))
-    ap.add_argument("--no-extra", action="store_true", help="skip the other three paths")
+    ap.add_argument("--no-extra", action="store_true", help="skip the other paths")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the batched tube ensemble and the serving trace")
@@ -271,10 +277,11 @@ def main():
         "value": res["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "fp32" if head["fp32"] else "fp64", "data": "synthetic",
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp16": "f32 (f16 storage)"}[head["store"]],
+        "data": "synthetic",
         "config": {"workload": res["workload"], "grid": list(head["shape"][:head["dim"]]),
                    "velocity_set": f"D{head['dim']}Q{37 if head['dim'] == 2 else 107}",
-                   "storage": "fp32 deviation" if head["fp32"] else "fp64",
+                   "storage": STORAGE[head["store"]][0],
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": res["gbs"], "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": res["hbm_frac"],

@@ -71,8 +71,14 @@ enum lbm_bc { LBM_BC_PERIODIC = 0, LBM_BC_ZERO_GRADIENT = 1 };
  * FP32_DEV: populations stored in float as deviations from the rest
  *   equilibrium, g_i - w_i and h_i - w_i delta/2 (reference rho0 = T0 = 1),
  *   collision in float computed directly on the deviations; readouts and
- *   conservation totals in double. */
-enum lbm_precision { LBM_FP64 = 0, LBM_FP32_DEV = 1 };
+ *   conservation totals in double.
+ * FP16_SCALED: as FP32_DEV, but each deviation is stored in IEEE half
+ *   precision divided by its weight w_i (the per-population scale that puts
+ *   all populations in one range); half the bytes of FP32_DEV, with the
+ *   accuracy of an 11-bit significand per stored value.  That rounding is
+ *   not conservative: totals drift at its level (a random walk of about
+ *   w_i |d_i| 2^-12 per stored value and step). */
+enum lbm_precision { LBM_FP64 = 0, LBM_FP32_DEV = 1, LBM_FP16_SCALED = 2 };
 
 /* Create a solve (Secs. II-IV).
  *   dim           2 or 3

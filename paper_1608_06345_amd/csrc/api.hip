@@ -44,10 +44,11 @@ int check_shape(int dim, int velocity_set, int precision, int64_t nx, int64_t ny
     if (dim == 2 && velocity_set != LBM_D2Q37) return LBM_EINVAL;
     if (dim == 3 && velocity_set != LBM_D3Q107) return LBM_EINVAL;
     if (dim != 2 && dim != 3) return LBM_EINVAL;
-    if (precision != LBM_FP64 && precision != LBM_FP32_DEV) return LBM_EINVAL;
+    if (precision != LBM_FP64 && precision != LBM_FP32_DEV && precision != LBM_FP16_SCALED)
+        return LBM_EINVAL;
     if (nx < 1 || ny < 1 || nz < 1) return LBM_EINVAL;
     if (dim == 2 && nz != 1) return LBM_EINVAL;
-    const size_t elem = precision == LBM_FP64 ? 8 : 4;
+    const size_t elem = precision == LBM_FP64 ? 8 : (precision == LBM_FP32_DEV ? 4 : 2);
     // one population plane must stay addressable with 32-bit byte offsets
     // (the kernels add a plane offset to a cell offset in 32 bits)
     if (nx > (1LL << 31) || ny > (1LL << 31) || nz > (1LL << 31)) return LBM_EINVAL;
@@ -103,6 +104,7 @@ int readout(lbm_solver* h, double* rho, double* u, double* E, bool totals) {
     a.open_end = (h->bc & 3u) | (((h->bc >> 2) & 3u) << 1) | (((h->bc >> 4) & 3u) << 2);
     a.r = h->lat->r;
     a.rest_energy = 0.5 * (h->dim + h->delta);
+    for (int g = 0; g < h->lat->groups; ++g) a.w[g] = h->lat->w_group[g];
     a.rho = rho;
     a.u = u;
     a.E = E;

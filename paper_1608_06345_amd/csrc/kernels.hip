@@ -69,52 +69,57 @@ __device__ __forceinline__ bool row_item(const StepArgs& a, int lane_cell, uint3
 }
 
 // Fused step, one lane per cell: the lane holds all 2Q populations.  A wave
-// serves 64 cells of one row.
-template <int D, typename T, bool DEV, int WAVES>
+// serves 64 cells of one row.  P is the storage precision (F64, F32Dev,
+// F16Dev).
+template <int D, class P, int WAVES>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
 void k_step(const StepArgs a) {
+    using T = typename P::T;
+    using S = typename P::S;
     constexpr int Q = VelSet<D>::Q;
-    RowOffsets<T> o;
+    RowOffsets<S> o;
     bool active;
-    if (!row_item<D, T, 64>(a, (int)threadIdx.x & 63, 0u, o, active)) return;
-    const uint32_t plane = (uint32_t)a.N * (uint32_t)sizeof(T);
+    if (!row_item<D, S, 64>(a, (int)threadIdx.x & 63, 0u, o, active)) return;
+    const uint32_t plane = (uint32_t)a.N * (uint32_t)sizeof(S);
     T g[Q], h[Q];
-    load_lane<D, T>(static_cast<const char*>(a.src), plane, o, g, h);
-    collide_lane<D, T, DEV>(g, h, a.ph);
+    load_lane<D, P>(static_cast<const char*>(a.src), plane, o, g, h, a.ph);
+    collide_lane<D, P>(g, h, a.ph);
     // Lanes past the end of a ragged row hold the row's last cell (clamped),
     // loaded and updated exactly like the lane that owns it, so they store
     // the same bits to the same place.  No branch: a branch here lets the
     // compiler sink the whole relaxation into the store block and keep every
     // target and population live at once.
     (void)active;
-    store_lane<D, T>(static_cast<char*>(a.dst), plane, o, g, h);
+    store_lane<D, P>(static_cast<char*>(a.dst), plane, o, g, h, a.ph);
 }
 
 // Fused step, split layout (see collide_split): a wave serves 32 cells of
 // one row.  This halves the registers a lane needs (Q instead of 2Q values).
-template <int D, typename T, bool DEV, int WAVES>
+template <int D, class P, int WAVES>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
 void k_step_split(const StepArgs a) {
+    using T = typename P::T;
+    using S = typename P::S;
     constexpr int Q = VelSet<D>::Q;
     const int lane = (int)threadIdx.x & 63;
     const int role = lane >> 5;  // 0: g, 1: h
-    const uint32_t plane = (uint32_t)a.N * (uint32_t)sizeof(T);
-    RowOffsets<T> o;
+    const uint32_t plane = (uint32_t)a.N * (uint32_t)sizeof(S);
+    RowOffsets<S> o;
     bool active;
-    if (!row_item<D, T, 32>(a, lane & 31, role ? plane : 0u, o, active)) return;
+    if (!row_item<D, S, 32>(a, lane & 31, role ? plane : 0u, o, active)) return;
     T p[Q];
-    load_split<D, T>(static_cast<const char*>(a.src), plane, o, p);
-    collide_split<D, T, DEV>(p, role, a.ph);
+    load_split<D, P>(static_cast<const char*>(a.src), plane, o, p, a.ph);
+    collide_split<D, P>(p, role, a.ph);
     // tail lanes store their clamped cell's identical update (see k_step)
     (void)active;
-    store_split<D, T>(static_cast<char*>(a.dst), plane, o, p);
+    store_split<D, P>(static_cast<char*>(a.dst), plane, o, p, a.ph);
 }
 
 // ---------------------------------------------------------------------------
 // Initial state S_0 = equilibrium of (rho, u, T), evaluated in double and
 // stored in the storage precision (deviation from the rest equilibrium in
 // FP32_DEV: g_i - w_i, h_i - (delta/2) w_i).
-template <int D, typename T, bool DEV>
+template <int D, class P>
 __global__ __launch_bounds__(256) void k_init(char* dst, const double* __restrict__ rho_in,
                                               const double* __restrict__ u_in,
                                               const double* __restrict__ T_in, int64_t N,
@@ -131,7 +136,8 @@ __global__ __launch_bounds__(256) void k_init(char* dst, const double* __restric
     Equilibrium<D, double, true> eq;  // deviation form, in double
     eq.setup(u, temp - 1.0, r);
     const double hdT = half_delta * temp;
-    const size_t plane = (size_t)N * sizeof(T);
+    using S = typename P::S;
+    const size_t plane = (size_t)N * sizeof(S);
     static_for<0, Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr Vel v = V.v[i];
@@ -142,7 +148,7 @@ __global__ __launch_bounds__(256) void k_init(char* dst, const double* __restric
         const double w = wg.w[v.group];
         const double Fdev = w * (rho * pm1 + (rho - 1.0));  // F_i - w_i
         double gv, hv;
-        if constexpr (DEV) {
+        if constexpr (P::kDev) {
             gv = Fdev;
             hv = hdT * Fdev + half_delta * w * (temp - 1.0);  // H_i - (delta/2) w_i
         } else {
@@ -150,8 +156,14 @@ __global__ __launch_bounds__(256) void k_init(char* dst, const double* __restric
             hv = hdT * (Fdev + w);
         }
         char* base = dst + (size_t)(2 * i) * plane;
-        reinterpret_cast<T*>(base)[cell] = T(gv);
-        reinterpret_cast<T*>(base + plane)[cell] = T(hv);
+        if constexpr (P::kScaled) {  // stored divided by w (see F16Dev)
+            gv /= w;
+            hv /= w;
+        }
+        // rounded once, from double, to the storage type (via float for half)
+        using Mid = std::conditional_t<sizeof(S) < 4, float, S>;
+        reinterpret_cast<S*>(base)[cell] = S(Mid(gv));
+        reinterpret_cast<S*>(base + plane)[cell] = S(Mid(hv));
     });
 }
 
@@ -159,7 +171,7 @@ __global__ __launch_bounds__(256) void k_init(char* dst, const double* __restric
 // Readout of S_n in double: per-cell rho, u, E and/or per-workgroup partial
 // totals (rho, rho u, rho E), reduced across the wave and the workgroup in a
 // fixed order.
-template <int D, typename T, bool DEV>
+template <int D, class P>
 __global__ __launch_bounds__(kReadBlock) void k_readout(const ReadArgs a) {
     constexpr VelSet<D> V = kVelSet<D>;
     constexpr int Q = VelSet<D>::Q;
@@ -173,16 +185,19 @@ __global__ __launch_bounds__(kReadBlock) void k_readout(const ReadArgs a) {
         coords((int)cell, a.nx, a.nxy, x, y, z);
         PullTable<D> pt;
         pt.fill(x, y, z, a.nx, a.ny, a.nz, a.nxy, a.open_end, a.stream != 0);
-        const uint32_t plane = (uint32_t)a.N * (uint32_t)sizeof(T);
+        using S = typename P::S;
+        constexpr bool DEV = P::kDev;
+        const uint32_t plane = (uint32_t)a.N * (uint32_t)sizeof(S);
         const char* src = static_cast<const char*>(a.src);
         double s0 = 0, sj[3] = {0, 0, 0}, se = 0, sh = 0;
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             constexpr Vel v = V.v[i];
-            const uint32_t off = (uint32_t)pt.template src<v.x, v.y, v.z>() * (uint32_t)sizeof(T);
+            const uint32_t off = (uint32_t)pt.template src<v.x, v.y, v.z>() * (uint32_t)sizeof(S);
             const char* base = src + (size_t)(2 * i) * plane;
-            const double gv = (double)load_at<T>(base, off);
-            const double hv = (double)load_at<T>(base, off + plane);
+            const double scale = P::kScaled ? a.w[v.group] : 1.0;
+            const double gv = (double)load_at<S>(base, off) * scale;
+            const double hv = (double)load_at<S>(base, off + plane) * scale;
             s0 += gv;
             if constexpr (v.x != 0) sj[0] += double(v.x) * gv;
             if constexpr (v.y != 0) sj[1] += double(v.y) * gv;
@@ -251,7 +266,7 @@ __global__ __launch_bounds__(256) void k_final_reduce(const double* __restrict__
     if (threadIdx.x < NT) out[threadIdx.x] = sm[0][threadIdx.x];
 }
 
-template <int D, typename T, bool DEV>
+template <int D, class P>
 hipError_t step_impl(bool split, const StepArgs& a0, hipStream_t s) {
     StepArgs a = a0;
     const int L = split ? 32 : 64;  // cells per wave
@@ -262,18 +277,26 @@ hipError_t step_impl(bool split, const StepArgs& a0, hipStream_t s) {
     // whole rows per XCD once there are enough rows to keep all eight busy
     a.xcd_rows = a.rows >= 64 ? 1 : 0;
     const int grid = a.xcd_rows ? 8 * a.tiles_per_row * ((a.rows + 7) / 8) : (a.items + 3) / 4;
-    // Occupancy hint for the split D3Q107 FP32 kernel: asking for at least
+    // Occupancy hint for the split D3Q107 float kernels: asking for at least
     // two waves per SIMD gave 4% more bandwidth than the compiler's own
     // choice (three waves at 162 VGPRs); the other kernels run best as
     // compiled.
-    constexpr int kSplitWaves = (D == 3 && sizeof(T) == 4) ? 2 : 1;
+    constexpr int kSplitWaves = (D == 3 && sizeof(typename P::T) == 4) ? 2 : 1;
     if (split)
-        return launch_kernel(&k_step_split<D, T, DEV, kSplitWaves>, dim3(grid), dim3(256), s, a);
+        return launch_kernel(&k_step_split<D, P, kSplitWaves>, dim3(grid), dim3(256), s, a);
     else
-        return launch_kernel(&k_step<D, T, DEV, 1>, dim3(grid), dim3(256), s, a);
+        return launch_kernel(&k_step<D, P, 1>, dim3(grid), dim3(256), s, a);
 }
 
 }  // namespace
+
+// Run `f` with the storage policy of `precision`.
+template <class F>
+hipError_t with_policy(int precision, F&& f) {
+    if (precision == LBM_FP64) return f(F64{});
+    if (precision == LBM_FP16_SCALED) return f(F16Dev{});
+    return f(F32Dev{});
+}
 
 hipError_t launch_init(int dim, int precision, void* dst, const double* rho,
                        const double* u, const double* T, int64_t N, double half_delta,
@@ -282,34 +305,29 @@ hipError_t launch_init(int dim, int precision, void* dst, const double* rho,
     for (int k = 0; k < 10; ++k) wg.w[k] = w_group[k];
     const int grid = (int)((N + 255) / 256);
     char* d = static_cast<char*>(dst);
-    if (dim == 2 && precision == LBM_FP64)
-        return launch_kernel(&k_init<2, double, false>, dim3(grid), dim3(256), s, d, rho, u, T, N, half_delta, r, wg);
-    else if (dim == 2)
-        return launch_kernel(&k_init<2, float, true>, dim3(grid), dim3(256), s, d, rho, u, T, N, half_delta, r, wg);
-    else if (precision == LBM_FP64)
-        return launch_kernel(&k_init<3, double, false>, dim3(grid), dim3(256), s, d, rho, u, T, N, half_delta, r, wg);
-    else
-        return launch_kernel(&k_init<3, float, true>, dim3(grid), dim3(256), s, d, rho, u, T, N, half_delta, r, wg);
+    return with_policy(precision, [&](auto pol) {
+        using P = decltype(pol);
+        if (dim == 2)
+            return launch_kernel(&k_init<2, P>, dim3(grid), dim3(256), s, d, rho, u, T, N, half_delta, r, wg);
+        return launch_kernel(&k_init<3, P>, dim3(grid), dim3(256), s, d, rho, u, T, N, half_delta, r, wg);
+    });
 }
 
 hipError_t launch_step(int dim, int precision, bool split, const StepArgs& a, hipStream_t s) {
-    if (dim == 2 && precision == LBM_FP64) return step_impl<2, double, false>(split, a, s);
-    if (dim == 2) return step_impl<2, float, true>(split, a, s);
-    if (precision == LBM_FP64) return step_impl<3, double, false>(split, a, s);
-    return step_impl<3, float, true>(split, a, s);
+    return with_policy(precision, [&](auto pol) {
+        using P = decltype(pol);
+        return dim == 2 ? step_impl<2, P>(split, a, s) : step_impl<3, P>(split, a, s);
+    });
 }
 
 int step_block_cells(int, int, bool split) { return split ? 128 : 256; }
 
 hipError_t launch_readout(int dim, int precision, const ReadArgs& a, int blocks, hipStream_t s) {
-    if (dim == 2 && precision == LBM_FP64)
-        return launch_kernel(&k_readout<2, double, false>, dim3(blocks), dim3(kReadBlock), s, a);
-    else if (dim == 2)
-        return launch_kernel(&k_readout<2, float, true>, dim3(blocks), dim3(kReadBlock), s, a);
-    else if (precision == LBM_FP64)
-        return launch_kernel(&k_readout<3, double, false>, dim3(blocks), dim3(kReadBlock), s, a);
-    else
-        return launch_kernel(&k_readout<3, float, true>, dim3(blocks), dim3(kReadBlock), s, a);
+    return with_policy(precision, [&](auto pol) {
+        using P = decltype(pol);
+        if (dim == 2) return launch_kernel(&k_readout<2, P>, dim3(blocks), dim3(kReadBlock), s, a);
+        return launch_kernel(&k_readout<3, P>, dim3(blocks), dim3(kReadBlock), s, a);
+    });
 }
 
 hipError_t launch_final_reduce(int dim, const double* partials, int blocks, double* out,

@@ -154,6 +154,7 @@ Physics physics_of(int dim, double delta, double tau_f, double tau_g) {
     for (int g = 0; g < t.groups; ++g) {
         ph.w[g] = t.w_group[g];
         ph.wf[g] = (float)t.w_group[g];
+        ph.inv_wf[g] = (float)(1.0 / t.w_group[g]);
     }
     return ph;
 }

@@ -38,6 +38,7 @@ struct Physics {
     double r;                 // lattice scale, xi = r e
     double w[10];             // group weights
     float wf[10];             // the same, rounded to float
+    float inv_wf[10];         // 1 / w (scaling of half-precision storage)
 };
 
 // Arguments of the fused step kernel (passed by value in the kernarg
@@ -69,7 +70,8 @@ struct ReadArgs {
     uint32_t open_end;
     int32_t stream;           // 1: the source holds P_{n-1}; pull to get S_n
     double r;
-    double rest_energy;       // (D + delta) / 2, added back in FP32_DEV mode
+    double rest_energy;       // (D + delta) / 2, added back in deviation storage
+    double w[10];             // group weights (scaled storage is divided by them)
     double* rho;              // [N] or null
     double* u;                // [D][N] or null
     double* E;                // [N] or null

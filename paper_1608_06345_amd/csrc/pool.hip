@@ -89,9 +89,11 @@ __device__ __forceinline__ bool pool_item(const SolveEntry& e, int local, int wa
 // One workgroup per tile: the grid of each launch is exactly the tile count
 // of the resident solves (a loop over tiles would keep loop state live
 // across the whole body and cost a wave per SIMD of occupancy).
-template <int D, typename T, bool DEV, bool SPLIT, int WAVES>
+template <int D, class P, bool SPLIT, int WAVES>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
 void k_pool_step(const PoolArgs pa) {
+    using T = typename P::T;
+    using S = typename P::S;
     constexpr int Q = VelSet<D>::Q;
     constexpr int L = SPLIT ? 32 : 64;
     const int tile = (int)blockIdx.x;
@@ -120,9 +122,9 @@ void k_pool_step(const PoolArgs pa) {
     const int z = row / e.ny;
     const int xr = seg * L + (SPLIT ? (lane & 31) : lane);
     const int x = xr < e.nx ? xr : e.nx - 1;  // tail lanes redo the last cell
-    const uint32_t plane = (uint32_t)e.N * (uint32_t)sizeof(T);
-    RowOffsets<T> o;
-    fill_row_offsets<D, T>(o, x, y, z, e.nx, e.ny, e.nz, e.nxy, e.open_end, true,
+    const uint32_t plane = (uint32_t)e.N * (uint32_t)sizeof(S);
+    RowOffsets<S> o;
+    fill_row_offsets<D, S>(o, x, y, z, e.nx, e.ny, e.nz, e.nxy, e.open_end, true,
                            role ? plane : 0u);
     const int par = (int)(done & 1);
     const char* src = reinterpret_cast<const char*>(e.base + (par ? e.side_bytes : 0));
@@ -134,14 +136,14 @@ void k_pool_step(const PoolArgs pa) {
     ph.inv_dof = e.inv_dof;
     if constexpr (SPLIT) {
         T p[Q];
-        load_split<D, T>(src, plane, o, p);
-        collide_split<D, T, DEV>(p, role, ph);
-        store_split<D, T>(dst, plane, o, p);
+        load_split<D, P>(src, plane, o, p, ph);
+        collide_split<D, P>(p, role, ph);
+        store_split<D, P>(dst, plane, o, p, ph);
     } else {
         T g[Q], h[Q];
-        load_lane<D, T>(src, plane, o, g, h);
-        collide_lane<D, T, DEV>(g, h, ph);
-        store_lane<D, T>(dst, plane, o, g, h);
+        load_lane<D, P>(src, plane, o, g, h, ph);
+        collide_lane<D, P>(g, h, ph);
+        store_lane<D, P>(dst, plane, o, g, h, ph);
     }
 }
 
@@ -156,18 +158,30 @@ __global__ __launch_bounds__(256) void k_advance(const SolveEntry* table, int64_
 // The step kernel of a velocity set, in the pool's precision: the same
 // layouts as the single-solve launches (one lane per cell for D2Q37, the g/h
 // lane-pair split for D3Q107).
-template <typename T, bool DEV>
-const void* pool_step_kernel(int dim) {
-    if (dim == 2) return reinterpret_cast<const void*>(&k_pool_step<2, T, DEV, false, 1>);
-    constexpr int w = sizeof(T) == 4 ? 2 : 1;
-    return reinterpret_cast<const void*>(&k_pool_step<3, T, DEV, true, w>);
+template <class P>
+const void* pool_step_kernel_p(int dim) {
+    if (dim == 2) return reinterpret_cast<const void*>(&k_pool_step<2, P, false, 1>);
+    constexpr int w = sizeof(typename P::T) == 4 ? 2 : 1;
+    return reinterpret_cast<const void*>(&k_pool_step<3, P, true, w>);
 }
 
-template <typename T, bool DEV>
-hipError_t launch_pool_step(int dim, const PoolArgs& a, int grid, hipStream_t s) {
-    if (dim == 2) return launch_kernel(&k_pool_step<2, T, DEV, false, 1>, dim3(grid), dim3(256), s, a);
-    constexpr int w = sizeof(T) == 4 ? 2 : 1;
-    return launch_kernel(&k_pool_step<3, T, DEV, true, w>, dim3(grid), dim3(256), s, a);
+const void* pool_step_kernel(int precision, int dim) {
+    if (precision == LBM_FP64) return pool_step_kernel_p<F64>(dim);
+    if (precision == LBM_FP16_SCALED) return pool_step_kernel_p<F16Dev>(dim);
+    return pool_step_kernel_p<F32Dev>(dim);
+}
+
+template <class P>
+hipError_t launch_pool_step_p(int dim, const PoolArgs& a, int grid, hipStream_t s) {
+    if (dim == 2) return launch_kernel(&k_pool_step<2, P, false, 1>, dim3(grid), dim3(256), s, a);
+    constexpr int w = sizeof(typename P::T) == 4 ? 2 : 1;
+    return launch_kernel(&k_pool_step<3, P, true, w>, dim3(grid), dim3(256), s, a);
+}
+
+hipError_t launch_pool_step(int precision, int dim, const PoolArgs& a, int grid, hipStream_t s) {
+    if (precision == LBM_FP64) return launch_pool_step_p<F64>(dim, a, grid, s);
+    if (precision == LBM_FP16_SCALED) return launch_pool_step_p<F16Dev>(dim, a, grid, s);
+    return launch_pool_step_p<F32Dev>(dim, a, grid, s);
 }
 
 struct Slot {
@@ -340,9 +354,7 @@ int enqueue_steps(lbm_pool* p, int ticks, int mask, hipStream_t s) {
             if (!(mask & (1 << d))) continue;
             const lbm::PoolArgs a = pool_args(p, d);
             const int grid = p->tiles_total[d] > 0 ? p->tiles_total[d] : 1;
-            hipError_t e = p->precision == LBM_FP64
-                               ? lbm::launch_pool_step<double, false>(d + 2, a, grid, s)
-                               : lbm::launch_pool_step<float, true>(d + 2, a, grid, s);
+            hipError_t e = lbm::launch_pool_step(p->precision, d + 2, a, grid, s);
             POOL_HIP(e);
         }
         POOL_HIP(lbm::launch_kernel(&lbm::k_advance, dim3((p->max_slots + 255) / 256), dim3(256),
@@ -389,6 +401,8 @@ int pool_readout(lbm_pool* p, int slot, double* rho, double* u, double* E, bool 
     a.open_end = e.open_end;
     a.r = lbm::lattice_tables(sl.dim).r;
     a.rest_energy = 0.5 * (sl.dim + sl.delta);
+    for (int g = 0; g < lbm::lattice_tables(sl.dim).groups; ++g)
+        a.w[g] = lbm::lattice_tables(sl.dim).w_group[g];
     a.rho = rho;
     a.u = u;
     a.E = E;
@@ -412,11 +426,12 @@ int lbm_pool_create(size_t budget_bytes, int max_slots, int precision, lbm_pool_
     if (!out) return LBM_EINVAL;
     *out = nullptr;
     if (max_slots < 1 || max_slots > 65536 || budget_bytes < 4096) return LBM_EINVAL;
-    if (precision != LBM_FP64 && precision != LBM_FP32_DEV) return LBM_EINVAL;
+    if (precision != LBM_FP64 && precision != LBM_FP32_DEV && precision != LBM_FP16_SCALED)
+        return LBM_EINVAL;
     lbm_pool* p = new (std::nothrow) lbm_pool;
     if (!p) return LBM_ENOMEM;
     p->precision = precision;
-    p->elem = precision == LBM_FP64 ? 8 : 4;
+    p->elem = precision == LBM_FP64 ? 8 : (precision == LBM_FP32_DEV ? 4 : 2);
     p->budget = budget_bytes & ~(size_t)255;
     p->max_slots = max_slots;
     p->slots.resize(max_slots);
@@ -479,11 +494,13 @@ int lbm_pool_set_stream(lbm_pool_handle p, void* stream) {
 }
 
 size_t lbm_pool_request_bytes(const lbm_request* r, int precision) {
-    if (!r || (precision != LBM_FP64 && precision != LBM_FP32_DEV)) return 0;
+    if (!r || (precision != LBM_FP64 && precision != LBM_FP32_DEV &&
+               precision != LBM_FP16_SCALED))
+        return 0;
     if (r->dim != 2 && r->dim != 3) return 0;
     if (r->nx < 1 || r->ny < 1 || r->nz < 1 || (r->dim == 2 && r->nz != 1)) return 0;
     const double N = (double)r->nx * (double)r->ny * (double)r->nz;
-    const size_t elem = precision == LBM_FP64 ? 8 : 4;
+    const size_t elem = precision == LBM_FP64 ? 8 : (precision == LBM_FP32_DEV ? 4 : 2);
     if (N * (double)elem > 2147483647.0) return 0;
     const int q = r->dim == 2 ? LBM_D2Q37 : LBM_D3Q107;
     const size_t bytes = 2 * 2 * (size_t)q * (size_t)N * elem;
@@ -667,8 +684,7 @@ int lbm_pool_run(lbm_pool_handle p, int ticks) {
         std::vector<hipGraphNode_t> nodes(n);
         POOL_HIP(hipGraphGetNodes(g, nodes.data(), &n));
         for (int d = 0; d < 2; ++d) {
-            const void* fn = p->precision == LBM_FP64 ? lbm::pool_step_kernel<double, false>(d + 2)
-                                                      : lbm::pool_step_kernel<float, true>(d + 2);
+            const void* fn = lbm::pool_step_kernel(p->precision, d + 2);
             for (auto node : nodes) {
                 hipGraphNodeType type;
                 POOL_HIP(hipGraphNodeGetType(node, &type));

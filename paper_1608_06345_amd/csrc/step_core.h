@@ -137,6 +137,29 @@ __device__ __forceinline__ double weight<double>(const Physics& ph, int g) { ret
 template <>
 __device__ __forceinline__ float weight<float>(const Physics& ph, int g) { return ph.wf[g]; }
 
+// Storage precisions.  T is the arithmetic type of the collision, S the type
+// a population is stored in.  F16 stores the deviation of a population from
+// its rest equilibrium divided by its weight, (g_i - w_i) / w_i and
+// (h_i - (delta/2) w_i) / w_i: dividing by w_i (which spans 3e-5 .. 0.2)
+// makes every population's stored value of the same size, so one half-
+// precision format serves all of them.  Loads multiply w_i back and the
+// collision runs in float exactly as for F32Dev.
+struct F64 {
+    using T = double;
+    using S = double;
+    static constexpr bool kDev = false, kScaled = false;
+};
+struct F32Dev {
+    using T = float;
+    using S = float;
+    static constexpr bool kDev = true, kScaled = false;
+};
+struct F16Dev {
+    using T = float;
+    using S = _Float16;
+    static constexpr bool kDev = true, kScaled = true;
+};
+
 // Moment sums over one set of Q populations p (scaled lattice units):
 // s0 = sum p, sj = sum e p, se = sum |e|^2 p.
 template <int D, typename T>
@@ -314,8 +337,11 @@ __device__ __forceinline__ void fill_row_offsets(RowOffsets<T>& o, int x, int y,
 }
 
 // Collision of one cell, one lane holding all 2Q populations (g and h).
-template <int D, typename T, bool DEV>
-__device__ __forceinline__ void collide_lane(T* g, T* h, const Physics& ph) {
+template <int D, class P>
+__device__ __forceinline__ void collide_lane(typename P::T* g, typename P::T* h,
+                                             const Physics& ph) {
+    using T = typename P::T;
+    constexpr bool DEV = P::kDev;
     T s0, sj[3] = {0, 0, 0}, se, sh, dummy_j[3], dummy_e;
     moment_sums<D, T>(g, s0, sj, se);
     moment_sums<D, T>(h, sh, dummy_j, dummy_e);
@@ -340,8 +366,10 @@ __device__ __forceinline__ void collide_lane(T* g, T* h, const Physics& ph) {
 // (role 1).  The moment sums are exchanged between the halves (lane ^ 32);
 // both halves evaluate the same equilibrium, each relaxes its own
 // distribution.  Every lane of the wave must take part (the exchange).
-template <int D, typename T, bool DEV>
-__device__ __forceinline__ void collide_split(T* p, int role, const Physics& ph) {
+template <int D, class P>
+__device__ __forceinline__ void collide_split(typename P::T* p, int role, const Physics& ph) {
+    using T = typename P::T;
+    constexpr bool DEV = P::kDev;
     T s0, sj[3] = {0, 0, 0}, se;
     moment_sums<D, T>(p, s0, sj, se);
     const T o0 = __shfl_xor(s0, 32);
@@ -371,51 +399,100 @@ __device__ __forceinline__ void collide_split(T* p, int role, const Physics& ph)
 }
 
 // Pull the lane's cell (lane layout): g and h of every population.
-template <int D, typename T>
-__device__ __forceinline__ void load_lane(const char* src, uint32_t plane, const RowOffsets<T>& o,
-                                          T* g, T* h) {
+// Half storage: each conversion and its weight scaling are one mixed-
+// precision FMA with a zero addend, written out as such:
+//   load   x = half(raw) * w_g          (v_fma_mix_f32, f16 source: exact
+//                                         widening, one rounding in float)
+//   store  raw = half(x * (1/w_g))       (v_fma_mixlo_f16: one rounding to
+//                                         half, round to nearest even)
+// The load converts in place (tied operand), so the load's destination
+// register becomes the float.  Left to itself the compiler folds the
+// conversions into the neighbouring FMAs instead, which keeps the half
+// values live beside their float copies and costs 60-80 registers (an
+// occupancy step).
+//
+// Stored value -> arithmetic value of a population of group g.
+template <class P>
+__device__ __forceinline__ typename P::T from_store(typename P::S raw, const Physics& ph, int g) {
+    using T = typename P::T;
+    if constexpr (P::kScaled) {
+        static_assert(std::is_same_v<typename P::S, _Float16> && std::is_same_v<T, float>);
+        float x = __builtin_bit_cast(float, (uint32_t)__builtin_bit_cast(uint16_t, raw));
+        asm("v_fma_mix_f32 %0, %0, %1, 0 op_sel_hi:[1,0,0]" : "+v"(x) : "s"(weight<T>(ph, g)));
+        return x;
+    } else {
+        return T(raw);
+    }
+}
+
+// Arithmetic value -> stored value.
+template <class P>
+__device__ __forceinline__ typename P::S to_store(typename P::T v, const Physics& ph, int g) {
+    if constexpr (P::kScaled) {
+        static_assert(std::is_same_v<typename P::S, _Float16> && std::is_same_v<typename P::T, float>);
+        _Float16 r;
+        asm("v_fma_mixlo_f16 %0, %1, %2, 0 op_sel_hi:[0,0,0]" : "=v"(r) : "v"(v), "s"(ph.inv_wf[g]));
+        return r;
+    } else {
+        return typename P::S(v);
+    }
+}
+
+template <int D, class P>
+__device__ __forceinline__ void load_lane(const char* src, uint32_t plane,
+                                          const RowOffsets<typename P::S>& o, typename P::T* g,
+                                          typename P::T* h, const Physics& ph) {
+    using S = typename P::S;
     constexpr VelSet<D> V = kVelSet<D>;
     static_for<0, VelSet<D>::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr Vel v = V.v[i];
         const char* base = src + (size_t)(2 * i) * plane + o.yo[v.y + 3] + o.zo[v.z + 3];
-        g[i] = load_at<T>(base, o.xo[v.x + 3]);
-        h[i] = load_at<T>(base + plane, o.xo[v.x + 3]);
+        g[i] = from_store<P>(load_at<S>(base, o.xo[v.x + 3]), ph, v.group);
+        h[i] = from_store<P>(load_at<S>(base + plane, o.xo[v.x + 3]), ph, v.group);
     });
 }
 
-template <int D, typename T>
-__device__ __forceinline__ void store_lane(char* dst, uint32_t plane, const RowOffsets<T>& o,
-                                           const T* g, const T* h) {
+template <int D, class P>
+__device__ __forceinline__ void store_lane(char* dst, uint32_t plane,
+                                           const RowOffsets<typename P::S>& o,
+                                           const typename P::T* g, const typename P::T* h,
+                                           const Physics& ph) {
+    constexpr VelSet<D> V = kVelSet<D>;
     char* row = dst + o.row;
     static_for<0, VelSet<D>::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
+        constexpr int grp = V.v[i].group;
         char* base = row + (size_t)(2 * i) * plane;
-        store_at<T>(base, o.own, g[i]);
-        store_at<T>(base + plane, o.own, h[i]);
+        store_at(base, o.own, to_store<P>(g[i], ph, grp));
+        store_at(base + plane, o.own, to_store<P>(h[i], ph, grp));
     });
 }
 
 // Pull the lane's half of its cell (split layout; the role offset is in o).
-template <int D, typename T>
+template <int D, class P>
 __device__ __forceinline__ void load_split(const char* src, uint32_t plane,
-                                           const RowOffsets<T>& o, T* p) {
+                                           const RowOffsets<typename P::S>& o, typename P::T* p,
+                                           const Physics& ph) {
+    using S = typename P::S;
     constexpr VelSet<D> V = kVelSet<D>;
     static_for<0, VelSet<D>::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr Vel v = V.v[i];
         const char* base = src + (size_t)(2 * i) * plane + o.yo[v.y + 3] + o.zo[v.z + 3];
-        p[i] = load_at<T>(base, o.xo[v.x + 3]);
+        p[i] = from_store<P>(load_at<S>(base, o.xo[v.x + 3]), ph, v.group);
     });
 }
 
-template <int D, typename T>
-__device__ __forceinline__ void store_split(char* dst, uint32_t plane, const RowOffsets<T>& o,
-                                            const T* p) {
+template <int D, class P>
+__device__ __forceinline__ void store_split(char* dst, uint32_t plane,
+                                            const RowOffsets<typename P::S>& o,
+                                            const typename P::T* p, const Physics& ph) {
+    constexpr VelSet<D> V = kVelSet<D>;
     char* row = dst + o.row;
     static_for<0, VelSet<D>::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        store_at<T>(row + (size_t)(2 * i) * plane, o.own, p[i]);
+        store_at(row + (size_t)(2 * i) * plane, o.own, to_store<P>(p[i], ph, V.v[i].group));
     });
 }
 

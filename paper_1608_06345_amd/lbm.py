@@ -27,7 +27,7 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ESTATE, LBM_ENONFINITE = 0, -1,
 LBM_EBUSY = -6
 LBM_D2Q37, LBM_D3Q107 = 37, 107
 LBM_BC_PERIODIC, LBM_BC_ZERO_GRADIENT = 0, 1
-LBM_FP64, LBM_FP32_DEV = 0, 1
+LBM_FP64, LBM_FP32_DEV, LBM_FP16_SCALED = 0, 1, 2
 LBM_VARIANT_AUTO, LBM_VARIANT_LANE, LBM_VARIANT_SPLIT = 0, 1, 2
 
 

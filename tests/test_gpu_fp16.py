@@ -1,0 +1,227 @@
+"""Half-precision storage (LBM_FP16_SCALED) on the GPU against the FP64
+oracle.
+
+Each population is stored as its deviation from the rest equilibrium divided
+by its weight, (g_i - w_i) / w_i and (h_i - (delta/2) w_i) / w_i, in IEEE
+half precision; the collision runs in float exactly as in FP32 deviation
+storage.  Every stored value is rounded to 11 significant bits, so the error
+against the oracle is set by that rounding, not by the arithmetic:
+
+  * at step 0 the moments of the stored state differ from the initial fields
+    by at most sum_i w_i |d_i| 2^-11 (d_i the scaled deviations the oracle
+    computes): checked exactly, cell by cell;
+  * after n steps the rounding noise of every step has been injected and
+    partly diffused; the bars below (TOL_FP16 for 1000-step smooth runs,
+    TOL_FP16_SHORT for runs of tens of steps) are a few times the errors
+    measured on these seeded cases.
+
+Results are bitwise deterministic and identical between the single-solve
+path and the batched pool, alone and in a mix."""
+import numpy as np
+import pytest
+
+from paper_1608_06345_amd import lbm
+from paper_1608_06345_amd.inputs import shear_wave_fields, smooth_fields, sod_fields
+from parity_util import assert_close, gpu_run, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+P16 = lbm.LBM_FP16_SCALED
+LANE, SPLIT = lbm.LBM_VARIANT_LANE, lbm.LBM_VARIANT_SPLIT
+TOL_FP16 = 5e-3
+TOL_FP16_SHORT = 1e-3
+U16 = 2.0 ** -11  # unit roundoff of IEEE half
+
+CASE2D = dict(shape=(125, 111, 1), gamma=1.4, tf=0.7, tg=0.8)
+CASE3D = dict(shape=(48, 13, 11), gamma=1.4, tf=0.6, tg=0.6)
+
+
+@pytest.mark.parametrize("variant", [LANE, SPLIT])
+def test_fp16_2d_smooth_1000_steps(variant):
+    c = CASE2D
+    f = smooth_fields(2, *c["shape"], seed=2, kmax=1)
+    o = oracle_run(2, c["gamma"], c["tf"], c["tg"], c["shape"], f, 1000)
+    g = gpu_run(2, c["gamma"], c["tf"], c["tg"], c["shape"], f, 1000, precision=P16,
+                variant=variant)
+    e = assert_close(g, o, TOL_FP16, "D2Q37 FP16")
+    print(f"\nPARITY D2Q37 1000 steps FP16 variant={variant} rho/u/T={e}")
+
+
+@pytest.mark.parametrize("variant", [SPLIT, LANE])
+def test_fp16_3d_smooth_1000_steps(variant):
+    c = CASE3D
+    f = shear_wave_fields(3, *c["shape"], seed=3)
+    o = oracle_run(3, c["gamma"], c["tf"], c["tg"], c["shape"], f, 1000)
+    g = gpu_run(3, c["gamma"], c["tf"], c["tg"], c["shape"], f, 1000, precision=P16,
+                variant=variant)
+    e = assert_close(g, o, TOL_FP16, "D3Q107 FP16")
+    print(f"\nPARITY D3Q107 1000 steps FP16 variant={variant} rho/u/T={e}")
+
+
+@pytest.mark.parametrize("dim,shape", [(2, (61, 53, 1)), (3, (23, 19, 17))])
+def test_fp16_initial_state_rounding_bound(dim, shape):
+    """Moments of S_0 as stored: within the half-precision rounding of each
+    scaled deviation, cell by cell (rho, rho u and rho E)."""
+    from oracle.model import OracleLBM
+    f = smooth_fields(dim, *shape, seed=17, a_rho=0.05, a_u=0.05, a_T=0.05)
+    o = OracleLBM(dim, 1.4, 0.7, 0.8, *shape)
+    o.init_fields(*f)
+    w = o._w[None, :]
+    hd = o.delta / 2.0
+    dg = (o.g - w) / w
+    dh = (o.h - hd * w) / w
+    # rounding once from double (via float) to half: <= |d| (2^-11 + 2^-24),
+    # plus half a subnormal step (2^-25) for values below 2^-14
+    err_g = w * (np.abs(dg) * (U16 + 2.0 ** -24) + 2.0 ** -25)
+    err_h = w * (np.abs(dh) * (U16 + 2.0 ** -24) + 2.0 ** -25)
+    e = o.lat.e.astype(np.float64)
+    r = o.lat.r
+    bound_rho = err_g.sum(axis=1) * (1 + 1e-9) + 1e-13
+    bound_j = (err_g @ np.abs(e)) * r * (1 + 1e-9) + 1e-13
+    bound_E = (0.5 * r * r * (err_g @ np.sum(e * e, axis=1)) + err_h.sum(axis=1)) * (1 + 1e-9) + 1e-13
+    rho_o, u_o, E_o = o.moments()
+    with lbm.Solver(dim, 1.4, 0.7, 0.8, *shape, precision=P16) as s:
+        s.init_fields(*f)
+        rho, u, E = s.moments()
+    assert np.all(np.abs(rho - rho_o) <= bound_rho)
+    for k in range(dim):
+        assert np.all(np.abs(rho * u[k] - rho_o * u_o[k]) <= bound_j[:, k] + bound_rho * np.abs(u_o[k]))
+    assert np.all(np.abs(rho * E - rho_o * E_o) <= bound_E)
+    used = np.max(np.abs(rho - rho_o) / bound_rho)
+    print(f"\nFP16 S_0 rounding D{dim}: max |drho| = {np.max(np.abs(rho - rho_o)):.3e}, "
+          f"{used:.2f} of the bound")
+    # and the bound is not vacuous: the stored state is not exact
+    assert np.max(np.abs(rho - rho_o)) > 0
+
+
+@pytest.mark.parametrize("dim,gamma,tf,tg", [(3, 5.0 / 3.0, 0.65, 0.65), (2, 2.0, 0.6, 0.9),
+                                             (3, 1.25, 0.9, 0.6)])
+def test_fp16_gamma_and_two_tau(dim, gamma, tf, tg):
+    shape = (24, 7, 5) if dim == 3 else (37, 29, 1)
+    f = shear_wave_fields(dim, *shape, seed=11)
+    o = oracle_run(dim, gamma, tf, tg, shape, f, 150)
+    g = gpu_run(dim, gamma, tf, tg, shape, f, 150, precision=P16)
+    e = assert_close(g, o, TOL_FP16, f"FP16 gamma {gamma}")
+    print(f"\nPARITY FP16 D{dim} gamma={gamma:.3f} tau={tf}/{tg} 150 steps rho/u/T={e}")
+
+
+@pytest.mark.parametrize("dim,shape,bc", [
+    (2, (1, 1, 1), 0), (2, (5, 1, 1), 0), (2, (4, 4, 1), lbm.LBM_BC(1, 1)),
+    (3, (1, 1, 1), 0), (3, (7, 6, 5), lbm.LBM_BC(1, 1, 1)), (3, (9, 2, 4), lbm.LBM_BC(1, 0, 1))])
+def test_fp16_tiny_and_open_grids(dim, shape, bc):
+    from parity_util import open_of
+    f = smooth_fields(dim, *shape, seed=13, a_rho=0.05, a_u=0.05, a_T=0.05)
+    o = oracle_run(dim, 1.4, 0.7, 0.75, shape, f, 12, open_end=open_of(bc))
+    g = gpu_run(dim, 1.4, 0.7, 0.75, shape, f, 12, bc=bc, precision=P16)
+    assert_close(g, o, TOL_FP16_SHORT, f"FP16 {shape} bc={bc}")
+
+
+def _l1_rel(a, b):
+    return float(np.sum(np.abs(a - b)) / np.sum(np.abs(b)))
+
+
+def test_fp16_sod_shock_tube():
+    """At a shock the pointwise difference measures where the front sits,
+    not how accurate the state is: 11-bit rounding moves the steep front by
+    a fraction of a cell, which is a difference of order the jump in the
+    one or two cells it crosses.  The bars are therefore on the L1 norm of
+    the difference over the tube, and on what matters physically: half
+    storage changes the scheme's own L1 error against the exact solution by
+    less than 5% (the FP64 oracle's L1 error is the reference)."""
+    from oracle.riemann import l1_errors, shock_tube_profile
+    shape = (200, 4, 1)
+    bc = lbm.LBM_BC(lbm.LBM_BC_ZERO_GRADIENT, lbm.LBM_BC_PERIODIC)
+    f = sod_fields(2, *shape)
+    o = oracle_run(2, 1.4, 0.6, 0.6, shape, f, 48, open_end=(True, False, False))
+    g = gpu_run(2, 1.4, 0.6, 0.6, shape, f, 48, bc=bc, precision=P16)
+    d = (_l1_rel(g[0], o[0]), _l1_rel(g[1], o[1]), _l1_rel(g[2], o[2]))
+    point = (np.max(np.abs(g[0] - o[0]) / o[0]), np.max(np.abs(g[1] - o[1])),
+             np.max(np.abs(g[2] - o[2]) / o[2]))
+    print(f"\nPARITY FP16 Sod 200x4 48 steps L1-relative rho/u/T={d} pointwise={point}")
+    assert max(d) < TOL_FP16
+    ex = shock_tube_profile((1, 0, 1), (0.125, 0, 0.1), 1.4, 200, 48, lbm.lbm_lattice(37)[2])
+    rho, u, T = g[0][:200], g[1][0][:200], g[2][:200]
+    l1 = l1_errors(rho, u, rho * T, *ex)
+    l1_o = l1_errors(o[0][:200], o[1][0][:200], (o[0] * o[2])[:200], *ex)
+    print(f"FP16 Sod L1 against the exact solution rho/u/p={l1} (FP64 oracle {l1_o})")
+    for a, b in zip(l1, l1_o):
+        assert abs(a - b) <= 0.05 * b, (l1, l1_o)
+    for y in range(1, 4):
+        assert np.array_equal(g[0][y * 200:(y + 1) * 200], g[0][:200])
+
+
+def test_fp16_deterministic_and_conservation():
+    shape = (40, 9, 1)
+    f = smooth_fields(2, *shape, seed=21)
+    a = gpu_run(2, 1.4, 0.7, 0.7, shape, f, 30, precision=P16)
+    b = gpu_run(2, 1.4, 0.7, 0.7, shape, f, 30, precision=P16)
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x, y)
+    g0 = gpu_run(2, 1.4, 0.7, 0.7, shape, f, 0, precision=P16)
+    # half storage does not conserve exactly: each step rounds every stored
+    # deviation independently (zero-mean); the totals drift like a random
+    # walk of per-cell size ~ w |d| 2^-12, far below 1e-6 of the mass here
+    m0, p0, e0 = g0[3]
+    m1, p1, e1 = a[3]
+    print(f"\nFP16 30-step drift: mass {abs(m1 - m0) / m0:.2e} energy {abs(e1 - e0) / e0:.2e}")
+    assert abs(m1 - m0) <= 1e-6 * m0
+    assert abs(e1 - e0) <= 1e-6 * e0
+
+
+def test_fp16_pool_alone_mix_and_single_solve():
+    """The pool in half storage: a request's result is bitwise the same
+    alone, in a mix, and through the single-solve path."""
+    OPEN_X = lbm.LBM_BC(lbm.LBM_BC_ZERO_GRADIENT, lbm.LBM_BC_PERIODIC)
+    reqs = [
+        (lbm.make_request(2, 1.4, 0.7, 0.8, 70, 45, steps=23), smooth_fields(2, 70, 45, seed=31)),
+        (lbm.make_request(3, 1.4, 0.65, 0.65, 24, 10, 9, steps=17),
+         shear_wave_fields(3, 24, 10, 9, seed=32)),
+        (lbm.make_request(2, 1.25, 0.8, 0.8, 300, 4, bc=OPEN_X, steps=40),
+         sod_fields(2, 300, 4, left=(1.0, 0.0, 1.2), right=(0.6, 0.0, 0.6))),
+        (lbm.make_request(2, 2.0, 0.6, 0.6, 128, 66, steps=31), shear_wave_fields(2, 128, 66, seed=35)),
+    ]
+
+    def run_to_end(pool, slots):
+        left = set(slots)
+        for _ in range(1000):
+            if not left:
+                return
+            pool.run(5)
+            left -= set(pool.poll())
+        raise AssertionError("pool did not finish")
+
+    alone = []
+    for r, f in reqs:
+        with lbm.Pool(1 << 30, 4, P16) as pool:
+            s = pool.admit(r, *f)
+            run_to_end(pool, [s])
+            alone.append(pool.moments(s))
+    with lbm.Pool(1 << 30, 8, P16) as pool:
+        slots = [pool.admit(r, *f) for r, f in reqs[:2]]
+        pool.run(5)
+        slots += [pool.admit(r, *f) for r, f in reqs[2:]]
+        res = {}
+        for _ in range(100):
+            if len(res) == len(reqs):
+                break
+            pool.run(5)
+            for s in pool.poll():
+                res[slots.index(s)] = pool.moments(s)
+                pool.release(s)
+    for k, (r, f) in enumerate(reqs):
+        with lbm.Solver(r.dim, r.gamma, r.tau_f, r.tau_g, r.nx, r.ny, r.nz, bc=r.bc,
+                        precision=P16) as sol:
+            sol.init_fields(*f)
+            sol.step(r.steps)
+            single = sol.moments()
+        for a, b, c in zip(alone[k], res[k], single):
+            assert np.all(np.isfinite(a))
+            assert np.array_equal(a, b), f"request {k}: alone != mix"
+            assert np.array_equal(a, c), f"request {k}: pool != single solve"
+    # and against the oracle, for the smooth 2D request
+    r, f = reqs[0]
+    o = oracle_run(2, r.gamma, r.tau_f, r.tau_g, (r.nx, r.ny, 1), f, r.steps)
+    rho, u, E = alone[0]
+    T = (2 * E - np.sum(u * u, axis=0)) / (2 + 2.0 / (r.gamma - 1.0) - 2)
+    e = assert_close((rho, u, T), o, TOL_FP16_SHORT, "FP16 pool vs oracle")
+    print(f"\nFP16 pool request vs oracle rho/u/T={e}")

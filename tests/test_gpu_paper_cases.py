@@ -23,7 +23,7 @@ LEFT, RIGHT = (4.0, 0.0, 4.0), (1.0, 0.0, 1.0)  # (rho, u, p), T = 1 on both sid
 
 
 @pytest.mark.parametrize("dim,shape", [(2, (1000, 16, 1)), (3, (1000, 16, 16))])
-@pytest.mark.parametrize("precision", [lbm.LBM_FP64, lbm.LBM_FP32_DEV])
+@pytest.mark.parametrize("precision", [lbm.LBM_FP64, lbm.LBM_FP32_DEV, lbm.LBM_FP16_SCALED])
 def test_paper_shock_tube(dim, shape, precision):
     from oracle.riemann import l1_errors, shock_tube_profile
     nx = shape[0]
@@ -48,8 +48,15 @@ def test_paper_shock_tube(dim, shape, precision):
     # a shock's steep front turns round-off differences in the moment sums
     # into slightly larger field differences than on smooth fields (1e-12);
     # FP32 as in the other shock-tube tests
-    tol = 1e-11 if precision == lbm.LBM_FP64 else 2e-3
     e = (np.max(np.abs(rho[:nx] - o[0]) / o[0]), np.max(np.abs(u[0][:nx] - o[1][0])),
          np.max(np.abs(T[:nx] - o[2]) / o[2]))
     print(f"PAPER CASE D{dim} precision={precision} vs oracle rho/u(abs)/T = {e}")
-    assert max(e) < tol
+    if precision == lbm.LBM_FP16_SCALED:
+        # half storage moves the fronts by a fraction of a cell: the bar is on
+        # the L1 norm of the difference (pointwise values reported above)
+        d = [float(np.sum(np.abs(a - b)) / np.sum(np.abs(b)))
+             for a, b in ((rho[:nx], o[0]), (u[0][:nx], o[1][0]), (T[:nx], o[2]))]
+        print(f"PAPER CASE D{dim} FP16 vs oracle, L1-relative rho/u/T = {d}")
+        assert max(d) < 1e-3
+    else:
+        assert max(e) < (1e-11 if precision == lbm.LBM_FP64 else 2e-3)
