@@ -22,6 +22,15 @@
  * One step is S_{n+1} = Stream(Collide(S_n)); the initial state is the
  * equilibrium of the initial fields.
  *
+ * The finite-difference form of Sec. III (orc_fd_step) advances the same two
+ * distributions explicitly in time with a free time step dt (grid step 1,
+ * particle speeds xi_i = r e_i):
+ *   g_i(t+dt) = g_i - dt xi_i . grad g_i - (dt/tau_f) (g_i - F_i),
+ *   h_i(t+dt) = h_i - dt xi_i . grad h_i - (dt/tau_g) (h_i - (delta/2) T F_i),
+ * everything on the right at time t, the convection term per axis by the
+ * third-order upwind-biased difference of Sec. III.  There tau_f and tau_g
+ * are relaxation times in the units of dt.
+ *
  * Boundary conditions, per axis: periodic (wrap) or open.  The paper leaves
  * the open condition unspecified (Sec. V); it is read as zero gradient: the
  * populations that stream in from beyond an open end are the post-collision
@@ -156,7 +165,8 @@ void orc_collide_cell(const orc_model *m, double *g, double *h)
 
 static long ncells(const orc_model *m) { return m->n[0] * m->n[1] * m->n[2]; }
 
-/* Pull source coordinate along one axis for destination x and shift e. */
+/* Pull source coordinate along one axis for destination x and shift e
+ * (also: the coordinate of the neighbour x + d is source_coord(x, -d, ...)). */
 static long source_coord(long x, long e, long n, int open_end)
 {
     long s = x - e;
@@ -231,6 +241,73 @@ int orc_step(const orc_model *m, double *g, double *h, long nsteps)
     }
     free(gp);
     free(hp);
+    return 0;
+}
+
+
+/* xi_a d(p)/dx_a of one population along one axis at x (Sec. III): the
+ * third-order upwind-biased difference, its stencil leaning against the
+ * direction of xi_a, grid step 1:
+ *   xi > 0:  xi [p(x-2) - 6 p(x-1) + 3 p(x) + 2 p(x+1)] / 6
+ *   xi < 0:  xi [-p(x+2) + 6 p(x+1) - 3 p(x) - 2 p(x-1)] / 6
+ * (the paper writes both halves at once with (xi +- |xi|)/2).  p_at(d)
+ * is the population at the neighbour x + d along the axis. */
+static double upwind_convection(double xi, const double p_at[5])
+{
+    /* p_at[d + 2] = p(x + d), d = -2..2 */
+    const double plus = (p_at[0] - 6.0 * p_at[1] + 3.0 * p_at[2] + 2.0 * p_at[3]) / 6.0;
+    const double minus = (-p_at[4] + 6.0 * p_at[3] - 3.0 * p_at[2] - 2.0 * p_at[1]) / 6.0;
+    return 0.5 * (xi + fabs(xi)) * plus + 0.5 * (xi - fabs(xi)) * minus;
+}
+
+/* nsteps explicit steps of the finite-difference form (see the header).
+ * Open ends: a neighbour beyond the end takes the end cell's value (zero
+ * gradient), the same reading as for streaming. */
+int orc_fd_step(const orc_model *m, double *g, double *h, long nsteps, double dt)
+{
+    const long N = ncells(m);
+    const int Q = m->Q, D = m->D;
+    double *gn = (double *)malloc(sizeof(double) * (size_t)(N * Q));
+    double *hn = (double *)malloc(sizeof(double) * (size_t)(N * Q));
+    if (!gn || !hn) { free(gn); free(hn); return -2; }
+    for (long step = 0; step < nsteps; ++step) {
+        #pragma omp parallel for schedule(static)
+        for (long c = 0; c < N; ++c) {
+            long x[3];
+            x[0] = c % m->n[0];
+            x[1] = (c / m->n[0]) % m->n[1];
+            x[2] = c / (m->n[0] * m->n[1]);
+            double rho, u[3] = {0.0, 0.0, 0.0}, E, T;
+            double F[ORC_QMAX];
+            orc_macro(m, g + c * Q, h + c * Q, &rho, u, &E, &T);
+            orc_feq(m, rho, u, T, F);
+            for (int i = 0; i < Q; ++i) {
+                double conv_g = 0.0, conv_h = 0.0;
+                for (int a = 0; a < D; ++a) {
+                    const double xi = m->r * (double)m->e[i * D + a];
+                    if (xi == 0.0) continue;
+                    double pg[5], ph[5];
+                    for (int d = -2; d <= 2; ++d) {
+                        long y[3] = {x[0], x[1], x[2]};
+                        y[a] = source_coord(x[a], -d, m->n[a], m->open_end[a]);
+                        const long nb = y[0] + m->n[0] * (y[1] + m->n[1] * y[2]);
+                        pg[d + 2] = g[nb * Q + i];
+                        ph[d + 2] = h[nb * Q + i];
+                    }
+                    conv_g += upwind_convection(xi, pg);
+                    conv_h += upwind_convection(xi, ph);
+                }
+                const double gi = g[c * Q + i], hi = h[c * Q + i];
+                gn[c * Q + i] = gi - dt * conv_g - dt / m->tau_f * (gi - F[i]);
+                hn[c * Q + i] = hi - dt * conv_h
+                              - dt / m->tau_g * (hi - 0.5 * m->delta * T * F[i]);
+            }
+        }
+        memcpy(g, gn, sizeof(double) * (size_t)(N * Q));
+        memcpy(h, hn, sizeof(double) * (size_t)(N * Q));
+    }
+    free(gn);
+    free(hn);
     return 0;
 }
 

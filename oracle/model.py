@@ -57,6 +57,8 @@ def _load():
         lib.orc_init.argtypes = [m, d, d, d, d, d]
         lib.orc_step.argtypes = [m, d, d, ctypes.c_long]
         lib.orc_step.restype = ctypes.c_int
+        lib.orc_fd_step.argtypes = [m, d, d, ctypes.c_long, ctypes.c_double]
+        lib.orc_fd_step.restype = ctypes.c_int
         lib.orc_moments.argtypes = [m, d, d, d, d, d]
         lib.orc_totals.argtypes = [m, d, d, d, d, d]
         lib.orc_num_threads.restype = ctypes.c_int
@@ -83,10 +85,15 @@ class OracleLBM:
     ``open_end``: per axis, True for the zero-gradient (open) end condition,
     False for periodic.  ``rho``/``T`` are ``[cells]`` and ``u`` is
     ``[dim][cells]`` with cell = x + nx (y + ny z).
+
+    ``dt``: None for the lattice scheme (collide, then stream e_i cells per
+    step; tau in lattice units), or the time step of the finite-difference
+    form of Sec. III (grid step 1, speeds xi_i = r e_i; tau_f and tau_g then
+    in the units of dt).
     """
 
     def __init__(self, dim, gamma, tau_f, tau_g, nx, ny, nz=1,
-                 open_end=(False, False, False), delta=None):
+                 open_end=(False, False, False), delta=None, dt=None):
         self.lat = lattice(dim)
         self.dim = dim
         self.delta = delta_from_gamma(gamma, dim) if delta is None else delta
@@ -111,6 +118,7 @@ class OracleLBM:
         self.g = np.zeros((self.ncells, self.lat.Q))
         self.h = np.zeros((self.ncells, self.lat.Q))
         self.steps = 0
+        self.dt = dt
 
     @property
     def Q(self):
@@ -158,8 +166,12 @@ class OracleLBM:
         self.h = np.ascontiguousarray(h, dtype=np.float64).reshape(self.ncells, self.Q).copy()
 
     def step(self, n=1):
-        rc = _load().orc_step(ctypes.byref(self._m), _dp(self.g), _dp(self.h),
-                              int(n))
+        if self.dt is None:
+            rc = _load().orc_step(ctypes.byref(self._m), _dp(self.g), _dp(self.h),
+                                  int(n))
+        else:
+            rc = _load().orc_fd_step(ctypes.byref(self._m), _dp(self.g), _dp(self.h),
+                                     int(n), float(self.dt))
         if rc != 0:
             raise MemoryError("oracle step could not allocate")
         self.steps += n
