@@ -43,6 +43,17 @@ for _store in ("fp32", "fp64", "fp16"):
                                     store=_store, seed=2, steps=1000)
 
 
+# The finite-difference form of Sec. III on the same grids and fields: time
+# step dt = c / (3r) with the fastest population's Courant number c = 0.25
+# (2D) and 0.3 (3D), relaxation times in the units of dt.
+_R = 1.196979770393074359
+for _store in ("fp32", "fp64"):
+    PATHS[f"d3q107_fd_{_store}"] = dict(dim=3, shape=(256, 256, 256), gamma=1.4, tf=0.12, tg=0.12,
+                                        store=_store, seed=3, steps=100, dt=0.3 / (3 * _R))
+    PATHS[f"d2q37_fd_{_store}"] = dict(dim=2, shape=(4096, 4096, 1), gamma=1.4, tf=0.1, tg=0.12,
+                                       store=_store, seed=2, steps=300, dt=0.25 / (3 * _R))
+
+
 def precision_of(store):
     from paper_1608_06345_amd import lbm
     return {"fp64": lbm.LBM_FP64, "fp32": lbm.LBM_FP32_DEV, "fp16": lbm.LBM_FP16_SCALED}[store]
@@ -57,8 +68,9 @@ def describe(name, p):
     q = 37 if p["dim"] == 2 else 107
     grid = "x".join(str(n) for n in p["shape"][:p["dim"]])
     delta = 2.0 / (p["gamma"] - 1.0) - p["dim"]
+    scheme = (f"finite-difference form, dt {p['dt']:.4f}, " if p.get("dt") else "")
     return (f"D{p['dim']}Q{q} {grid} periodic, smooth seeded field (seed {p['seed']}), "
-            f"gamma {p['gamma']} (delta {delta:g}), tau_f {p['tf']}, tau_g {p['tg']}, "
+            f"{scheme}gamma {p['gamma']} (delta {delta:g}), tau_f {p['tf']}, tau_g {p['tg']}, "
             f"{STORAGE[p['store']][0]}")
 
 
@@ -98,7 +110,8 @@ def run_path(name, p, steps, warmup):
     prec = precision_of(p["store"])
     f = smooth_fields(p["dim"], nx, ny, nz, seed=p["seed"])
     stream = torch.cuda.Stream()  # the kernels' stream; the events go on it too
-    with lbm.Solver(p["dim"], p["gamma"], p["tf"], p["tg"], nx, ny, nz, precision=prec) as s:
+    with lbm.Solver(p["dim"], p["gamma"], p["tf"], p["tg"], nx, ny, nz, precision=prec,
+                    dt=p.get("dt")) as s:
         s.set_stream(stream)
         dev = [torch.from_numpy(a.reshape(-1)).to("cuda") for a in f]
         torch.cuda.synchronize()

@@ -101,6 +101,37 @@ int lbm_create_ex(int dim, int velocity_set, double gamma, double tau_f,
                   double tau_g, int64_t nx, int64_t ny, int64_t nz,
                   uint32_t bc, int precision, lbm_handle *out);
 
+/* Create a solve that advances by the finite-difference form of Sec. III
+ * instead of lattice streaming: explicit Euler in time with step dt,
+ *   g_i(t+dt) = g_i - dt xi_i . grad g_i - (dt/tau_f) (g_i - F_i),
+ *   h_i(t+dt) = h_i - dt xi_i . grad h_i - (dt/tau_g) (h_i - (delta/2) T F_i),
+ * every term at time t, the convection per axis by the third-order
+ * upwind-biased difference of Sec. III (stencil x-2s .. x+s against the
+ * sign s of xi_a).  Units: grid step 1, particle speeds xi_i = r e_i, so one
+ * lattice step of lbm_create corresponds to dt = 1/r; tau_f and tau_g are
+ * relaxation times in the units of dt (no half-step shift).  Open ends take
+ * a neighbour beyond the end as the end cell's value (zero gradient).
+ *   dt      time step, 0 < dt <= 1/(3r) (the fastest speed, 3r, then moves
+ *           at most one cell per step)
+ *   tau_f, tau_g   > 0 with dt/tau <= 1 (the explicit relaxation must not
+ *           overshoot the equilibrium)
+ * Stability: forward Euler with the upwind-biased difference alone
+ * amplifies every mode; the relaxation damps the departures from
+ * equilibrium, and the scheme is stable for per-axis Courant numbers
+ * |xi_a| dt up to ~0.6-0.7 at dt/tau in 0.2-1 (less with weaker damping):
+ * for the fastest D2Q37 population (3r, 3r) that is 3 r dt <= ~0.3, for
+ * D3Q107's (3r, r, r) 3 r dt <= ~0.36.  Larger steps are accepted up to the
+ * bound below but grow without limit.
+ * precision: LBM_FP64 or LBM_FP32_DEV; LBM_FP16_SCALED is rejected (EINVAL):
+ * re-rounding every value to half at each of the many short steps costs
+ * percents of the velocity.
+ * Other arguments and errors as lbm_create_ex.  lbm_step(n) takes
+ * n such steps; lbm_moments and lbm_totals report the state at step n;
+ * init_fields sets the state to the equilibrium of the fields. */
+int lbm_create_fd(int dim, int velocity_set, double gamma, double tau_f,
+                  double tau_g, double dt, int64_t nx, int64_t ny, int64_t nz,
+                  uint32_t bc, int precision, lbm_handle *out);
+
 /* Release every device resource of the handle (NULL is accepted). */
 int lbm_destroy(lbm_handle h);
 
@@ -156,6 +187,8 @@ typedef struct {
     double gamma, delta, tau_f, tau_g, r;
     int64_t steps;          /* steps taken since the last init */
     size_t device_bytes;    /* device memory held by the handle */
+    int scheme;             /* 0: lattice streaming, 1: finite differences */
+    double dt;              /* finite-difference time step (0 for lattice) */
 } lbm_info;
 int lbm_get_info(lbm_handle h, lbm_info *info);
 

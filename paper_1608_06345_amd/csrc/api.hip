@@ -85,7 +85,7 @@ lbm::StepArgs step_args(const lbm_solver* h, const void* src, void* dst, bool st
     a.nxy = (int32_t)(h->nx * h->ny);
     a.open_end = (h->bc & 3u) | (((h->bc >> 2) & 3u) << 1) | (((h->bc >> 4) & 3u) << 2);
     a.stream = stream ? 1 : 0;
-    a.ph = lbm::physics_of(h->dim, h->delta, h->tau_f, h->tau_g);
+    a.ph = lbm::physics_of(h->dim, h->delta, h->tau_f, h->tau_g, h->scheme ? h->dt : 0.0);
     return a;
 }
 
@@ -93,9 +93,15 @@ lbm::StepArgs step_args(const lbm_solver* h, const void* src, void* dst, bool st
 int readout(lbm_solver* h, double* rho, double* u, double* E, bool totals) {
     lbm::ReadArgs a;
     std::memset(&a, 0, sizeof(a));
-    // S_0 sits unstreamed in the idle side; later S_n = Stream(P_{n-1}).
-    a.src = h->buf[h->cur ^ 1];
-    a.stream = h->initial ? 0 : 1;
+    // Lattice scheme: S_0 sits unstreamed in the idle side; later
+    // S_n = Stream(P_{n-1}).  Finite differences: S_n itself is current.
+    if (h->scheme) {
+        a.src = h->buf[h->cur];
+        a.stream = 0;
+    } else {
+        a.src = h->buf[h->cur ^ 1];
+        a.stream = h->initial ? 0 : 1;
+    }
     a.N = h->N;
     a.nx = (int32_t)h->nx;
     a.ny = (int32_t)h->ny;
@@ -115,6 +121,10 @@ int readout(lbm_solver* h, double* rho, double* u, double* E, bool totals) {
                                          h->stream));
     return LBM_OK;
 }
+
+int create_solver(int dim, int velocity_set, double gamma, double tau_f, double tau_g, double dt,
+                  int64_t nx, int64_t ny, int64_t nz, uint32_t bc, int precision,
+                  lbm_handle* out);
 
 }  // namespace
 
@@ -163,13 +173,43 @@ int lbm_create_ex(int dim, int velocity_set, double gamma, double tau_f, double 
                   lbm_handle* out) {
     if (!out) return LBM_EINVAL;
     *out = nullptr;
+    if (!(tau_f > 0.5) || !(tau_g > 0.5) || !std::isfinite(tau_f) || !std::isfinite(tau_g))
+        return LBM_EINVAL;
+    return create_solver(dim, velocity_set, gamma, tau_f, tau_g, 0.0, nx, ny, nz, bc, precision,
+                         out);
+}
+
+int lbm_create_fd(int dim, int velocity_set, double gamma, double tau_f, double tau_g, double dt,
+                  int64_t nx, int64_t ny, int64_t nz, uint32_t bc, int precision,
+                  lbm_handle* out) {
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    if (dim != 2 && dim != 3) return LBM_EINVAL;
+    const double r = lbm::lattice_tables(dim).r;
+    if (!std::isfinite(dt) || !(dt > 0.0) || dt * 3.0 * r > 1.0 + 1e-12) return LBM_EINVAL;
+    if (!std::isfinite(tau_f) || !std::isfinite(tau_g) || !(tau_f > 0.0) || !(tau_g > 0.0) ||
+        dt > tau_f || dt > tau_g)
+        return LBM_EINVAL;
+    // Half storage re-rounds every value each step, and the stable time step
+    // of this form is ~10x shorter than a lattice step: the rounding, then
+    // differenced with weights up to 6, costs percents of the velocity.
+    if (precision == LBM_FP16_SCALED) return LBM_EINVAL;
+    return create_solver(dim, velocity_set, gamma, tau_f, tau_g, dt, nx, ny, nz, bc, precision,
+                         out);
+}
+
+}  // extern "C"
+
+namespace {
+
+int create_solver(int dim, int velocity_set, double gamma, double tau_f, double tau_g, double dt,
+                  int64_t nx, int64_t ny, int64_t nz, uint32_t bc, int precision,
+                  lbm_handle* out) {
     Shape s;
     int rc = check_shape(dim, velocity_set, precision, nx, ny, nz, &s);
     if (rc != LBM_OK) return rc;
     double delta;
     if (!delta_of(gamma, dim, &delta)) return LBM_EINVAL;
-    if (!(tau_f > 0.5) || !(tau_g > 0.5) || !std::isfinite(tau_f) || !std::isfinite(tau_g))
-        return LBM_EINVAL;
     if (bc & ~0x3Fu) return LBM_EINVAL;
     for (int k = 0; k < 3; ++k)
         if (((bc >> (2 * k)) & 3u) > LBM_BC_ZERO_GRADIENT) return LBM_EINVAL;
@@ -190,6 +230,8 @@ int lbm_create_ex(int dim, int velocity_set, double gamma, double tau_f, double 
     h->delta = delta;
     h->tau_f = tau_f;
     h->tau_g = tau_g;
+    h->scheme = dt > 0.0 ? 1 : 0;
+    h->dt = dt;
     h->lat = &lbm::lattice_tables(dim);
     h->elem = s.elem;
     h->buf_bytes = 2 * (size_t)s.q * (size_t)s.N * s.elem;
@@ -218,6 +260,10 @@ int lbm_create_ex(int dim, int velocity_set, double gamma, double tau_f, double 
     *out = h;
     return LBM_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int lbm_create(int dim, int velocity_set, double gamma, double tau_f, double tau_g, int64_t nx,
                int64_t ny, int64_t nz, uint32_t bc, lbm_handle* out) {
@@ -264,6 +310,13 @@ int lbm_init_fields_dev(lbm_handle h, const double* rho, const double* u, const 
     // every step, with the pull switched off).
     LBM_HIP(lbm::launch_init(h->dim, h->precision, h->buf[0], rho, u, T, h->N, 0.5 * h->delta,
                              h->lat->r, h->lat->w_group, h->stream));
+    if (h->scheme) {  // finite differences keep S_n itself
+        h->cur = 0;
+        h->initial = true;
+        h->have_state = true;
+        h->steps = 0;
+        return LBM_OK;
+    }
     const lbm::StepArgs a = step_args(h, h->buf[0], h->buf[1], false);
     LBM_HIP(lbm::launch_step(h->dim, h->precision, h->split, a, h->stream));
     h->cur = 1;
@@ -295,7 +348,10 @@ int lbm_step(lbm_handle h, int64_t n) {
     if (!h->have_state) return LBM_ESTATE;
     for (int64_t k = 0; k < n; ++k) {
         const lbm::StepArgs a = step_args(h, h->buf[h->cur], h->buf[h->cur ^ 1], true);
-        LBM_HIP(lbm::launch_step(h->dim, h->precision, h->split, a, h->stream));
+        if (h->scheme)
+            LBM_HIP(lbm::launch_fd_step(h->dim, h->precision, h->split, a, h->stream));
+        else
+            LBM_HIP(lbm::launch_step(h->dim, h->precision, h->split, a, h->stream));
         h->cur ^= 1;
         h->initial = false;
         ++h->steps;
@@ -362,6 +418,8 @@ int lbm_get_info(lbm_handle h, lbm_info* info) {
     info->r = h->lat->r;
     info->steps = h->steps;
     info->device_bytes = h->device_bytes;
+    info->scheme = h->scheme;
+    info->dt = h->dt;
     return LBM_OK;
 }
 

@@ -168,6 +168,61 @@ __global__ __launch_bounds__(256) void k_init(char* dst, const double* __restric
 }
 
 // ---------------------------------------------------------------------------
+// The finite-difference form (Sec. III): explicit Euler in time, third-order
+// upwind-biased convection per axis, BGK with rates dt / tau.  A wave loads
+// the centre values of its cells, collides them in registers (taking the
+// convection centre term with them), then reads each population's upwind
+// neighbours from the time-n state and stores the new value.  The
+// neighbour reads come from cache.  Waves go out in launch order (row by
+// row).  Ordering them in per-XCD y bands, whole or in x-chunks, was
+// measured: at most 5% faster in 3D, 9% slower in 2D.  The rows around the
+// cells in flight on one XCD, over all 2Q planes, exceed its L2 either way.
+template <int D, typename S, int L>
+__device__ __forceinline__ bool fd_item(const StepArgs& a, int lane_cell, uint32_t role_off,
+                                        RowOffsets<S>& o) {
+    const int item = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (item >= a.items) return false;
+    int seg = item % a.segs;
+    const int row = item / a.segs;
+    int y = row % a.ny;
+    int z = row / a.ny;
+    seg = __builtin_amdgcn_readfirstlane(seg);
+    y = __builtin_amdgcn_readfirstlane(y);
+    z = __builtin_amdgcn_readfirstlane(z);
+    const int xr = seg * L + lane_cell;
+    const int x = xr < a.nx ? xr : a.nx - 1;  // tail lanes repeat the last cell
+    fill_row_offsets<D, S>(o, x, y, z, a.nx, a.ny, a.nz, a.nxy, a.open_end, true, role_off);
+    return true;
+}
+
+template <int D, class P, bool SPLIT, int WAVES>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
+void k_fd_step(const StepArgs a) {
+    using T = typename P::T;
+    using S = typename P::S;
+    constexpr int Q = VelSet<D>::Q;
+    const int lane = (int)threadIdx.x & 63;
+    const uint32_t plane = (uint32_t)a.N * (uint32_t)sizeof(S);
+    const char* src = static_cast<const char*>(a.src);
+    char* dst = static_cast<char*>(a.dst);
+    RowOffsets<S> o;
+    if constexpr (SPLIT) {
+        const int role = lane >> 5;  // 0: g, 1: h (see collide_split)
+        if (!fd_item<D, S, 32>(a, lane & 31, role ? plane : 0u, o)) return;
+        T p[Q];
+        load_split<D, P, false>(src, plane, o, p, a.ph);
+        collide_split<D, P, true>(p, role, a.ph);
+        convect_store_split<D, P>(src, dst, plane, o, p, a.ph);
+    } else {
+        if (!fd_item<D, S, 64>(a, lane, 0u, o)) return;
+        T g[Q], h[Q];
+        load_lane<D, P, false>(src, plane, o, g, h, a.ph);
+        collide_lane<D, P, true>(g, h, a.ph);
+        convect_store_lane<D, P>(src, dst, plane, o, g, h, a.ph);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Readout of S_n in double: per-cell rho, u, E and/or per-workgroup partial
 // totals (rho, rho u, rho E), reduced across the wave and the workgroup in a
 // fixed order.
@@ -288,6 +343,20 @@ hipError_t step_impl(bool split, const StepArgs& a0, hipStream_t s) {
         return launch_kernel(&k_step<D, P, 1>, dim3(grid), dim3(256), s, a);
 }
 
+template <int D, class P>
+hipError_t fd_step_impl(bool split, const StepArgs& a0, hipStream_t s) {
+    StepArgs a = a0;
+    const int L = split ? 32 : 64;
+    a.segs = (a.nx + L - 1) / L;
+    a.rows = a.ny * a.nz;
+    a.items = a.segs * a.rows;
+    a.tiles_per_row = (a.segs + 3) / 4;
+    a.xcd_rows = 0;
+    const int grid = (a.items + 3) / 4;
+    if (split) return launch_kernel(&k_fd_step<D, P, true, 1>, dim3(grid), dim3(256), s, a);
+    return launch_kernel(&k_fd_step<D, P, false, 1>, dim3(grid), dim3(256), s, a);
+}
+
 }  // namespace
 
 // Run `f` with the storage policy of `precision`.
@@ -321,6 +390,13 @@ hipError_t launch_step(int dim, int precision, bool split, const StepArgs& a, hi
 }
 
 int step_block_cells(int, int, bool split) { return split ? 128 : 256; }
+
+hipError_t launch_fd_step(int dim, int precision, bool split, const StepArgs& a, hipStream_t s) {
+    return with_policy(precision, [&](auto pol) {
+        using P = decltype(pol);
+        return dim == 2 ? fd_step_impl<2, P>(split, a, s) : fd_step_impl<3, P>(split, a, s);
+    });
+}
 
 hipError_t launch_readout(int dim, int precision, const ReadArgs& a, int blocks, hipStream_t s) {
     return with_policy(precision, [&](auto pol) {

@@ -142,12 +142,17 @@ std::once_flag g_once;
 
 }  // namespace
 
-Physics physics_of(int dim, double delta, double tau_f, double tau_g) {
+Physics physics_of(int dim, double delta, double tau_f, double tau_g, double dt) {
     const LatticeTables& t = lattice_tables(dim);
     Physics ph;
     std::memset(&ph, 0, sizeof(ph));
-    ph.omega_f = 1.0 / tau_f;
-    ph.omega_g = 1.0 / tau_g;
+    // lattice scheme: one lattice time step per step, rates 1/tau; the
+    // finite-difference form: rates dt/tau and convection dt xi . grad
+    const double step = dt > 0.0 ? dt : 1.0;
+    ph.omega_f = step / tau_f;
+    ph.omega_g = step / tau_g;
+    ph.fd_cs = dt > 0.0 ? dt * t.r / 6.0 : 0.0;
+    ph.fd_csf = (float)ph.fd_cs;
     ph.half_delta = 0.5 * delta;
     ph.inv_dof = 1.0 / (dim + delta);
     ph.r = t.r;

@@ -32,13 +32,15 @@ struct WGroups {
 
 // Physical parameters of one solve as the collision uses them.
 struct Physics {
-    double omega_f, omega_g;  // 1 / tau
+    double omega_f, omega_g;  // 1 / tau (lattice scheme), dt / tau (finite differences)
     double half_delta;        // delta / 2
     double inv_dof;           // 1 / (D + delta)
     double r;                 // lattice scale, xi = r e
     double w[10];             // group weights
     float wf[10];             // the same, rounded to float
     float inv_wf[10];         // 1 / w (scaling of half-precision storage)
+    double fd_cs;             // finite differences: dt r / 6 (0 for the lattice scheme)
+    float fd_csf;             // the same, rounded to float
 };
 
 // Arguments of the fused step kernel (passed by value in the kernarg
@@ -59,8 +61,9 @@ struct StepArgs {
     Physics ph;
 };
 
-// Collision parameters of a solve (lattice.cpp).
-Physics physics_of(int dim, double delta, double tau_f, double tau_g);
+// Collision parameters of a solve (lattice.cpp).  dt > 0 selects the
+// finite-difference form: relaxation rates dt / tau, convection scale dt r / 6.
+Physics physics_of(int dim, double delta, double tau_f, double tau_g, double dt = 0.0);
 
 // Arguments of the readout kernel (moments and conservation partials).
 struct ReadArgs {
@@ -101,6 +104,10 @@ hipError_t launch_init(int dim, int precision, void* dst, const double* rho,
                        hipStream_t s);
 hipError_t launch_step(int dim, int precision, bool split, const StepArgs& a,
                        hipStream_t s);
+// One explicit finite-difference step (Sec. III); sets the wave mapping
+// fields of a copy of `a`.
+hipError_t launch_fd_step(int dim, int precision, bool split, const StepArgs& a,
+                          hipStream_t s);
 int step_block_cells(int dim, int precision, bool split);
 hipError_t launch_readout(int dim, int precision, const ReadArgs& a,
                           int blocks, hipStream_t s);
@@ -124,6 +131,8 @@ struct lbm_solver {
     bool have_state;
     bool initial;         // buf[cur ^ 1] holds S_0 itself (no step yet)
     int64_t steps;
+    int scheme;           // 0: lattice (collide, stream), 1: finite differences
+    double dt;            // finite-difference time step (grid step 1, speeds r e)
     double* partials;     // readout block partials
     double* totals;       // [D + 2] final totals (device)
     int read_blocks;

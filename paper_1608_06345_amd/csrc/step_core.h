@@ -184,6 +184,19 @@ __device__ __forceinline__ void moment_sums(const T* p, T& s0, T* sj, T& se) {
     se = ae;
 }
 
+// |e|_1 of a lattice vector.
+__host__ __device__ constexpr int l1_of(Vel v) {
+    return (v.x < 0 ? -v.x : v.x) + (v.y < 0 ? -v.y : v.y) + (v.z < 0 ? -v.z : v.z);
+}
+
+// Convection scale dt r / 6 of the finite-difference form, in T.
+template <typename T>
+__device__ __forceinline__ T fd_scale(const Physics& ph);
+template <>
+__device__ __forceinline__ double fd_scale<double>(const Physics& ph) { return ph.fd_cs; }
+template <>
+__device__ __forceinline__ float fd_scale<float>(const Physics& ph) { return ph.fd_csf; }
+
 // Relax one set of populations toward their BGK targets with rate omega:
 //   t_i = w_i (alpha rho P~(c_i) + beta),
 // i.e. t_i = F_i for g (alpha = 1) and t_i = (delta/2) T F_i for h
@@ -204,12 +217,27 @@ __device__ __forceinline__ void moment_sums(const T* p, T& s0, T* sj, T& se) {
 //            no momentum).
 // je_on = 0 restricts the correction to the mass (used for h, whose only
 // conserved moment is its sum).
-template <int D, typename T, bool DEV>
+//
+// FD (the finite-difference form, Sec. III): omega is dt / tau, and each
+// population also loses the centre term of its upwind-biased convection,
+// 3 |e_i|_1 (dt r / 6) p_i, taken from the pre-collision value; the
+// neighbour terms are added by convect_store_* below.
+template <int D, typename T, bool DEV, bool FD = false>
 __device__ __forceinline__ void relax(T* p, const Equilibrium<D, T, DEV>& eq,
                                       const Physics& a, T arho, T beta, T omega, T want_m,
                                       const T* want_j, T want_e, T je_on) {
     constexpr VelSet<D> V = kVelSet<D>;
     constexpr int G = VelSet<D>::G;
+    // p + omega (t - p), less the convection centre term in FD
+    auto update = [&](T& pi, T t, auto L1) {
+        constexpr int l1 = decltype(L1)::value;
+        if constexpr (FD && l1 != 0) {
+            const T kc = T(3 * l1) * fd_scale<T>(a);
+            pi = (pi - kc * pi) + omega * (t - pi);
+        } else {
+            pi = pi + omega * (t - pi);
+        }
+    };
     static_assert(V.v[1].group == 1 && V.v[2 * D].group == 1 && V.v[2 * D + 1].group == 2,
                   "the axis populations must follow the rest population");
     T sm = 0, sjx = 0, sjy = 0, sjz = 0, se = 0;
@@ -242,8 +270,8 @@ __device__ __forceinline__ void relax(T* p, const Equilibrium<D, T, DEV>& eq,
                 t1[i - 1] = tp;
                 t1[i] = tm;
             } else {
-                p[i] = p[i] + omega * (tp - p[i]);
-                p[i + 1] = p[i + 1] + omega * (tm - p[i + 1]);
+                update(p[i], tp, std::integral_constant<int, l1_of(v)>{});
+                update(p[i + 1], tm, std::integral_constant<int, l1_of(v)>{});
             }
         });
     });
@@ -265,11 +293,11 @@ __device__ __forceinline__ void relax(T* p, const Equilibrium<D, T, DEV>& eq,
             const T half = T(0.5) * dj[axis];
             const T tp = t1[2 * k] + de_axis + half;
             const T tm = t1[2 * k + 1] + de_axis - half;
-            p[1 + 2 * k] = p[1 + 2 * k] + omega * (tp - p[1 + 2 * k]);
-            p[2 + 2 * k] = p[2 + 2 * k] + omega * (tm - p[2 + 2 * k]);
+            update(p[1 + 2 * k], tp, std::integral_constant<int, 1>{});
+            update(p[2 + 2 * k], tm, std::integral_constant<int, 1>{});
         });
     }
-    p[0] = p[0] + omega * (t0 - p[0]);
+    update(p[0], t0, std::integral_constant<int, 0>{});
 }
 
 // Macroscopic state of a cell from the moment sums.
@@ -337,7 +365,7 @@ __device__ __forceinline__ void fill_row_offsets(RowOffsets<T>& o, int x, int y,
 }
 
 // Collision of one cell, one lane holding all 2Q populations (g and h).
-template <int D, class P>
+template <int D, class P, bool FD = false>
 __device__ __forceinline__ void collide_lane(typename P::T* g, typename P::T* h,
                                              const Physics& ph) {
     using T = typename P::T;
@@ -356,8 +384,8 @@ __device__ __forceinline__ void collide_lane(typename P::T* g, typename P::T* h,
     const T beta_g = DEV ? drho : T(0);
     const T beta_h = DEV ? hdT * drho + hd * t : T(0);
     const T want_e = (rho * eq.U + T(D) * (drho + rho * t)) / eq.r2;
-    relax<D, T, DEV>(g, eq, ph, rho, beta_g, T(ph.omega_f), drho, sj, want_e, T(1));
-    relax<D, T, DEV>(h, eq, ph, hdT * rho, beta_h, T(ph.omega_g), hd * (drho + rho * t), sj,
+    relax<D, T, DEV, FD>(g, eq, ph, rho, beta_g, T(ph.omega_f), drho, sj, want_e, T(1));
+    relax<D, T, DEV, FD>(h, eq, ph, hdT * rho, beta_h, T(ph.omega_g), hd * (drho + rho * t), sj,
                      T(0), T(0));
 }
 
@@ -366,7 +394,7 @@ __device__ __forceinline__ void collide_lane(typename P::T* g, typename P::T* h,
 // (role 1).  The moment sums are exchanged between the halves (lane ^ 32);
 // both halves evaluate the same equilibrium, each relaxes its own
 // distribution.  Every lane of the wave must take part (the exchange).
-template <int D, class P>
+template <int D, class P, bool FD = false>
 __device__ __forceinline__ void collide_split(typename P::T* p, int role, const Physics& ph) {
     using T = typename P::T;
     constexpr bool DEV = P::kDev;
@@ -394,7 +422,7 @@ __device__ __forceinline__ void collide_split(typename P::T* p, int role, const 
     const T beta = DEV ? (role ? hdT * drho + hd * t : drho) : T(0);
     const T want_e = (rho * eq.U + T(D) * (drho + rho * t)) / eq.r2;
     const T want_m = role ? hd * (drho + rho * t) : drho;
-    relax<D, T, DEV>(p, eq, ph, arho, beta, role ? T(ph.omega_g) : T(ph.omega_f), want_m, gj,
+    relax<D, T, DEV, FD>(p, eq, ph, arho, beta, role ? T(ph.omega_g) : T(ph.omega_f), want_m, gj,
                      want_e, role ? T(0) : T(1));
 }
 
@@ -438,7 +466,9 @@ __device__ __forceinline__ typename P::S to_store(typename P::T v, const Physics
     }
 }
 
-template <int D, class P>
+// PULL = false reads every population at the cell itself (the centre values
+// of the finite-difference form).
+template <int D, class P, bool PULL = true>
 __device__ __forceinline__ void load_lane(const char* src, uint32_t plane,
                                           const RowOffsets<typename P::S>& o, typename P::T* g,
                                           typename P::T* h, const Physics& ph) {
@@ -447,9 +477,10 @@ __device__ __forceinline__ void load_lane(const char* src, uint32_t plane,
     static_for<0, VelSet<D>::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr Vel v = V.v[i];
-        const char* base = src + (size_t)(2 * i) * plane + o.yo[v.y + 3] + o.zo[v.z + 3];
-        g[i] = from_store<P>(load_at<S>(base, o.xo[v.x + 3]), ph, v.group);
-        h[i] = from_store<P>(load_at<S>(base + plane, o.xo[v.x + 3]), ph, v.group);
+        constexpr int kx = PULL ? v.x + 3 : 3, ky = PULL ? v.y + 3 : 3, kz = PULL ? v.z + 3 : 3;
+        const char* base = src + (size_t)(2 * i) * plane + o.yo[ky] + o.zo[kz];
+        g[i] = from_store<P>(load_at<S>(base, o.xo[kx]), ph, v.group);
+        h[i] = from_store<P>(load_at<S>(base + plane, o.xo[kx]), ph, v.group);
     });
 }
 
@@ -470,7 +501,7 @@ __device__ __forceinline__ void store_lane(char* dst, uint32_t plane,
 }
 
 // Pull the lane's half of its cell (split layout; the role offset is in o).
-template <int D, class P>
+template <int D, class P, bool PULL = true>
 __device__ __forceinline__ void load_split(const char* src, uint32_t plane,
                                            const RowOffsets<typename P::S>& o, typename P::T* p,
                                            const Physics& ph) {
@@ -479,8 +510,9 @@ __device__ __forceinline__ void load_split(const char* src, uint32_t plane,
     static_for<0, VelSet<D>::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr Vel v = V.v[i];
-        const char* base = src + (size_t)(2 * i) * plane + o.yo[v.y + 3] + o.zo[v.z + 3];
-        p[i] = from_store<P>(load_at<S>(base, o.xo[v.x + 3]), ph, v.group);
+        constexpr int kx = PULL ? v.x + 3 : 3, ky = PULL ? v.y + 3 : 3, kz = PULL ? v.z + 3 : 3;
+        const char* base = src + (size_t)(2 * i) * plane + o.yo[ky] + o.zo[kz];
+        p[i] = from_store<P>(load_at<S>(base, o.xo[kx]), ph, v.group);
     });
 }
 
@@ -493,6 +525,86 @@ __device__ __forceinline__ void store_split(char* dst, uint32_t plane,
     static_for<0, VelSet<D>::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         store_at(row + (size_t)(2 * i) * plane, o.own, to_store<P>(p[i], ph, V.v[i].group));
+    });
+}
+
+
+// ---------------------------------------------------------------------------
+// The finite-difference form (Sec. III): after the collision (which already
+// took the centre term), each population loses the neighbour terms of its
+// third-order upwind-biased convection, read from the time-n state:
+//   dt xi_a d(p)/dx_a = (dt r / 6) |e_a| [p(x - 2s) - 6 p(x - s) + 3 p(x) + 2 p(x + s)],
+// s = sign(e_a), per axis with e_a != 0 (the stencil leans against the
+// flow).  Neighbour x + d along an axis is offset index 3 - d (offsets hold
+// x - e for e = -3..3, wrapped or clamped like the pull).
+
+// Neighbour part  sum_a |e_a| [p(x - 2s) - 6 p(x - s) + 2 p(x + s)]  of
+// population V at the plane starting at `sp`.
+template <int D, class P, int I>
+__device__ __forceinline__ typename P::T fd_neighbours(const char* sp,
+                                                       const RowOffsets<typename P::S>& o,
+                                                       const Physics& ph) {
+    using T = typename P::T;
+    using S = typename P::S;
+    constexpr Vel v = kVelSet<D>.v[I];
+    T nb = T(0);
+    static_for<0, D>([&](auto A) {
+        constexpr int a = decltype(A)::value;
+        constexpr int e = a == 0 ? v.x : (a == 1 ? v.y : v.z);
+        if constexpr (e != 0) {
+            constexpr int s = e > 0 ? 1 : -1;
+            constexpr int m = e > 0 ? e : -e;
+            auto at = [&](auto Dd) {
+                constexpr int d = decltype(Dd)::value;
+                const uint32_t xo = a == 0 ? o.xo[3 - d] : o.xo[3];
+                const uint32_t yo = a == 1 ? o.yo[3 - d] : o.yo[3];
+                const uint32_t zo = a == 2 ? o.zo[3 - d] : o.zo[3];
+                return from_store<P>(load_at<S>(sp + yo + zo, xo), ph, v.group);
+            };
+            const T far = at(std::integral_constant<int, -2 * s>{});
+            const T near = at(std::integral_constant<int, -s>{});
+            const T ahead = at(std::integral_constant<int, s>{});
+            nb += T(m) * ((far - T(6) * near) + T(2) * ahead);
+        }
+    });
+    return nb;
+}
+
+template <int D, class P>
+__device__ __forceinline__ void convect_store_split(const char* src, char* dst, uint32_t plane,
+                                                    const RowOffsets<typename P::S>& o,
+                                                    const typename P::T* p, const Physics& ph) {
+    using T = typename P::T;
+    constexpr VelSet<D> V = kVelSet<D>;
+    const T cs = fd_scale<T>(ph);
+    char* row = dst + o.row;
+    static_for<0, VelSet<D>::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        const char* sp = src + (size_t)(2 * i) * plane;
+        const T nb = fd_neighbours<D, P, i>(sp, o, ph);
+        store_at(row + (size_t)(2 * i) * plane, o.own,
+                 to_store<P>(p[i] - cs * nb, ph, V.v[i].group));
+    });
+}
+
+template <int D, class P>
+__device__ __forceinline__ void convect_store_lane(const char* src, char* dst, uint32_t plane,
+                                                   const RowOffsets<typename P::S>& o,
+                                                   const typename P::T* g,
+                                                   const typename P::T* h, const Physics& ph) {
+    using T = typename P::T;
+    constexpr VelSet<D> V = kVelSet<D>;
+    const T cs = fd_scale<T>(ph);
+    char* row = dst + o.row;
+    static_for<0, VelSet<D>::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int grp = V.v[i].group;
+        const char* sp = src + (size_t)(2 * i) * plane;
+        const T nbg = fd_neighbours<D, P, i>(sp, o, ph);
+        const T nbh = fd_neighbours<D, P, i>(sp + plane, o, ph);
+        char* base = row + (size_t)(2 * i) * plane;
+        store_at(base, o.own, to_store<P>(g[i] - cs * nbg, ph, grp));
+        store_at(base + plane, o.own, to_store<P>(h[i] - cs * nbh, ph, grp));
     });
 }
 

@@ -53,7 +53,8 @@ class _Info(ctypes.Structure):
                 ("bc", ctypes.c_uint32),
                 ("gamma", ctypes.c_double), ("delta", ctypes.c_double),
                 ("tau_f", ctypes.c_double), ("tau_g", ctypes.c_double), ("r", ctypes.c_double),
-                ("steps", ctypes.c_int64), ("device_bytes", ctypes.c_size_t)]
+                ("steps", ctypes.c_int64), ("device_bytes", ctypes.c_size_t),
+                ("scheme", ctypes.c_int), ("dt", ctypes.c_double)]
 
 
 class lbm_request(ctypes.Structure):
@@ -78,6 +79,8 @@ def _load():
     sig = {
         "lbm_create": [i32, i32, d, d, d, i64, i64, i64, ctypes.c_uint32, ctypes.POINTER(vp)],
         "lbm_create_ex": [i32, i32, d, d, d, i64, i64, i64, ctypes.c_uint32, i32,
+                          ctypes.POINTER(vp)],
+        "lbm_create_fd": [i32, i32, d, d, d, d, i64, i64, i64, ctypes.c_uint32, i32,
                           ctypes.POINTER(vp)],
         "lbm_destroy": [vp],
         "lbm_set_stream": [vp, vp],
@@ -155,6 +158,25 @@ def lbm_create_ex(dim, velocity_set, gamma, tau_f, tau_g, nx, ny, nz, bc, precis
     _check(_lib.lbm_create_ex(dim, velocity_set, gamma, tau_f, tau_g, nx, ny, nz, bc,
                               precision, ctypes.byref(h)), "lbm_create_ex")
     return h
+
+
+def lbm_create_fd(dim, velocity_set, gamma, tau_f, tau_g, dt, nx, ny, nz, bc, precision):
+    h = ctypes.c_void_p()
+    _check(_lib.lbm_create_fd(dim, velocity_set, gamma, tau_f, tau_g, dt, nx, ny, nz, bc,
+                              precision, ctypes.byref(h)), "lbm_create_fd")
+    return h
+
+
+def lbm_create_fd_rc(dim, velocity_set, gamma, tau_f, tau_g, dt, nx, ny, nz, bc,
+                     precision=LBM_FP64):
+    """Raw status code of lbm_create_fd (for error-path tests); destroys a
+    handle that was created."""
+    h = ctypes.c_void_p()
+    rc = _lib.lbm_create_fd(dim, velocity_set, gamma, tau_f, tau_g, dt, nx, ny, nz, bc,
+                            precision, ctypes.byref(h))
+    if rc == LBM_OK:
+        _lib.lbm_destroy(h)
+    return rc
 
 
 def lbm_create(dim, velocity_set, gamma, tau_f, tau_g, nx, ny, nz, bc):
@@ -266,11 +288,17 @@ def lbm_lattice(velocity_set):
 
 
 class Solver:
-    """One solve behind a handle; closes it on ``close()`` / exit."""
+    """One solve behind a handle; closes it on ``close()`` / exit.  With
+    ``dt`` it advances by the finite-difference form (``lbm_create_fd``),
+    else by lattice streaming."""
 
-    def __init__(self, dim, gamma, tau_f, tau_g, nx, ny, nz=1, bc=0, precision=LBM_FP64):
+    def __init__(self, dim, gamma, tau_f, tau_g, nx, ny, nz=1, bc=0, precision=LBM_FP64,
+                 dt=None):
         vs = LBM_D2Q37 if dim == 2 else LBM_D3Q107
-        self.h = lbm_create_ex(dim, vs, gamma, tau_f, tau_g, nx, ny, nz, bc, precision)
+        if dt is None:
+            self.h = lbm_create_ex(dim, vs, gamma, tau_f, tau_g, nx, ny, nz, bc, precision)
+        else:
+            self.h = lbm_create_fd(dim, vs, gamma, tau_f, tau_g, dt, nx, ny, nz, bc, precision)
         self.dim = dim
         self.ncells = nx * ny * nz
 

@@ -16,9 +16,10 @@ TOL_FP32 = 1e-5
 
 
 def gpu_run(dim, gamma, tf, tg, shape, fields, steps, bc=0, precision=lbm.LBM_FP64,
-            variant=lbm.LBM_VARIANT_AUTO):
+            variant=lbm.LBM_VARIANT_AUTO, dt=None):
+    """``dt`` selects the finite-difference form (lbm_create_fd)."""
     nx, ny, nz = shape
-    with lbm.Solver(dim, gamma, tf, tg, nx, ny, nz, bc=bc, precision=precision) as s:
+    with lbm.Solver(dim, gamma, tf, tg, nx, ny, nz, bc=bc, precision=precision, dt=dt) as s:
         s.set_variant(variant)
         s.init_fields(*fields)
         s.step(steps)
@@ -28,9 +29,10 @@ def gpu_run(dim, gamma, tf, tg, shape, fields, steps, bc=0, precision=lbm.LBM_FP
     return rho, u, T, tot
 
 
-def oracle_run(dim, gamma, tf, tg, shape, fields, steps, open_end=(False, False, False)):
+def oracle_run(dim, gamma, tf, tg, shape, fields, steps, open_end=(False, False, False),
+               dt=None):
     from oracle.model import OracleLBM
-    o = OracleLBM(dim, gamma, tf, tg, *shape, open_end=open_end)
+    o = OracleLBM(dim, gamma, tf, tg, *shape, open_end=open_end, dt=dt)
     o.init_fields(*fields)
     o.step(steps)
     rho, u, E = o.moments()
@@ -72,20 +74,20 @@ def periodic_window(fields, shape, dim, center, half):
     return rho[cell], u[:, cell], T[cell]
 
 
-def oracle_sample(dim, gamma, tf, tg, fields, shape, centers, steps):
+def oracle_sample(dim, gamma, tf, tg, fields, shape, centers, steps, dt=None):
     """Oracle moments at sampled cells of a periodic grid after ``steps``
     steps, each from its own window: a cell's state after n steps depends
     only on the initial data within 3n cells (populations move at most 3
-    cells per step), so a window of half-width 3n reproduces it exactly --
-    whatever happens at the window's own edges reaches at most 3n - 1 cells
-    inward in n steps."""
-    half = 3 * steps
+    cells per step; the finite-difference stencil reaches 2 cells), so a
+    window of that half-width reproduces it exactly -- whatever happens at
+    the window's own edges reaches at most that far inward in n steps."""
+    half = (3 if dt is None else 2) * steps
     w = 2 * half + 1
     out = []
     for c in centers:
         f = periodic_window(fields, shape, dim, c, half)
         wshape = (w, w, w if dim == 3 else 1)
-        rho, u, T, _ = oracle_run(dim, gamma, tf, tg, wshape, f, steps)
+        rho, u, T, _ = oracle_run(dim, gamma, tf, tg, wshape, f, steps, dt=dt)
         mid = half + w * half + (w * w * half if dim == 3 else 0)
         out.append((rho[mid], u[:, mid], T[mid]))
     return out

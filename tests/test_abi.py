@@ -87,3 +87,32 @@ def test_invalid_precision_and_null_handles():
     assert lib.lbm_set_variant(None, 0) == lbm.LBM_EINVAL
     assert lbm.lbm_strerror(lbm.LBM_ENONFINITE).startswith("non-finite")
     assert lbm.lbm_strerror(12345) == "unknown status"
+
+
+R = 1.196979770393074359  # lattice scale; the FD time step is bounded by 1 / (3 r)
+
+
+@pytest.mark.parametrize("args", [
+    (2, 37, 1.4, 0.5, 0.5, 0.0, 8, 8, 1, 0),                # dt = 0
+    (2, 37, 1.4, 0.5, 0.5, -0.1, 8, 8, 1, 0),               # dt < 0
+    (2, 37, 1.4, 0.5, 0.5, float("nan"), 8, 8, 1, 0),
+    (2, 37, 1.4, 0.5, 0.5, 1.0 / (3 * R) * 1.01, 8, 8, 1, 0),  # fastest speed > 1 cell/step
+    (3, 107, 1.4, 0.05, 0.5, 0.1, 8, 8, 8, 0),              # dt / tau_f > 1
+    (2, 37, 1.4, 0.5, 0.09, 0.1, 8, 8, 1, 0),               # dt / tau_g > 1
+    (2, 37, 1.4, 0.0, 0.5, 0.1, 8, 8, 1, 0),                # tau <= 0
+    (2, 107, 1.4, 0.5, 0.5, 0.1, 8, 8, 1, 0),               # dim / velocity set mismatch
+    (3, 107, 1.7, 0.5, 0.5, 0.1, 8, 8, 8, 0),               # delta < 0
+    (2, 37, 1.4, 0.5, 0.5, 0.1, 8, 8, 2, 0),                # nz != 1 in 2D
+    (2, 37, 1.4, 0.5, 0.5, 0.1, 8, 8, 1, 2),                # unknown bc code
+    (5, 37, 1.4, 0.5, 0.5, 0.1, 8, 8, 1, 0),
+])
+def test_create_fd_rejects_invalid_arguments(args):
+    assert lbm.lbm_create_fd_rc(*args) == lbm.LBM_EINVAL
+    assert lbm.lbm_create_fd_rc(*args, precision=lbm.LBM_FP32_DEV) == lbm.LBM_EINVAL
+    assert lbm.lbm_create_fd_rc(*args[:6], 8, 8, 1, 0, precision=9) == lbm.LBM_EINVAL
+
+
+def test_create_fd_refuses_half_storage():
+    # valid in every other respect: half storage alone is refused
+    assert lbm.lbm_create_fd_rc(2, 37, 1.4, 0.1, 0.1, 0.07, 8, 8, 1, 0,
+                                precision=lbm.LBM_FP16_SCALED) == lbm.LBM_EINVAL
