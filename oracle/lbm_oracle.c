@@ -59,6 +59,7 @@ typedef struct {
     double tau_g;      /* relaxation time of h */
     long n[3];         /* grid size per axis; n[2] = 1 in 2D */
     int open_end[3];   /* 1: zero-gradient (open) axis, 0: periodic */
+    int energy_fix;    /* 1: energy-conserving collision for tau_f != tau_g */
 } orc_model;
 
 int orc_num_threads(void)
@@ -149,17 +150,49 @@ void orc_macro(const orc_model *m, const double *g, const double *h,
     *T_out = (2.0 * E - U) / (D + m->delta);
 }
 
+/* Energy-conserving collision (not part of the paper; a separate mode).
+ * With rates a_f, a_g (1/tau, or dt/tau in the finite-difference form) the
+ * BGK step changes the cell's total energy by
+ *   (a_f - a_g) (E_tr^eq - E_tr),   E_tr = sum xi^2 g / 2,
+ * E_tr^eq = rho (u^2 + D T) / 2 its equilibrium value, because the internal
+ * part sum h relaxes at the other rate toward the complement.  Relaxing h
+ * toward ((delta/2) T + kappa) F instead, with
+ *   kappa rho = (1 - a_f / a_g) (E_tr^eq - E_tr),
+ * makes the step conserve energy exactly; kappa = 0 when tau_f = tau_g.
+ * Returns kappa (0 when the mode is off). */
+static double energy_fix_kappa(const orc_model *m, const double *g, double rho,
+                               const double *u, double T)
+{
+    if (!m->energy_fix) return 0.0;
+    const int D = m->D;
+    double e_tr = 0.0, U = 0.0;
+    for (int i = 0; i < m->Q; ++i) {
+        double q = 0.0;
+        for (int k = 0; k < D; ++k) {
+            const double xi = m->r * (double)m->e[i * D + k];
+            q += xi * xi;
+        }
+        e_tr += 0.5 * q * g[i];
+    }
+    for (int k = 0; k < D; ++k) U += u[k] * u[k];
+    const double e_tr_eq = 0.5 * rho * (U + D * T);
+    /* a_f / a_g = tau_g / tau_f in both forms */
+    return (1.0 - m->tau_g / m->tau_f) * (e_tr_eq - e_tr) / rho;
+}
+
 /* BGK relaxation of one cell in place (Sec. II reduced equations, explicit
- * in time as in Sec. III): g toward F, h toward (delta/2) T F. */
+ * in time as in Sec. III): g toward F, h toward (delta/2) T F (plus kappa F
+ * in the energy-conserving mode). */
 void orc_collide_cell(const orc_model *m, double *g, double *h)
 {
     double rho, u[3], E, T;
     double F[ORC_QMAX];
     orc_macro(m, g, h, &rho, u, &E, &T);
     orc_feq(m, rho, u, T, F);
+    const double kappa = energy_fix_kappa(m, g, rho, u, T);
     for (int i = 0; i < m->Q; ++i) {
         g[i] = g[i] - (g[i] - F[i]) / m->tau_f;
-        h[i] = h[i] - (h[i] - 0.5 * m->delta * T * F[i]) / m->tau_g;
+        h[i] = h[i] - (h[i] - (0.5 * m->delta * T + kappa) * F[i]) / m->tau_g;
     }
 }
 
@@ -281,6 +314,7 @@ int orc_fd_step(const orc_model *m, double *g, double *h, long nsteps, double dt
             double F[ORC_QMAX];
             orc_macro(m, g + c * Q, h + c * Q, &rho, u, &E, &T);
             orc_feq(m, rho, u, T, F);
+            const double kappa = energy_fix_kappa(m, g + c * Q, rho, u, T);
             for (int i = 0; i < Q; ++i) {
                 double conv_g = 0.0, conv_h = 0.0;
                 for (int a = 0; a < D; ++a) {
@@ -300,7 +334,7 @@ int orc_fd_step(const orc_model *m, double *g, double *h, long nsteps, double dt
                 const double gi = g[c * Q + i], hi = h[c * Q + i];
                 gn[c * Q + i] = gi - dt * conv_g - dt / m->tau_f * (gi - F[i]);
                 hn[c * Q + i] = hi - dt * conv_h
-                              - dt / m->tau_g * (hi - 0.5 * m->delta * T * F[i]);
+                              - dt / m->tau_g * (hi - (0.5 * m->delta * T + kappa) * F[i]);
             }
         }
         memcpy(g, gn, sizeof(double) * (size_t)(N * Q));

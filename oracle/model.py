@@ -37,7 +37,8 @@ class _Model(ctypes.Structure):
                 ("w", ctypes.POINTER(ctypes.c_double)),
                 ("r", ctypes.c_double), ("delta", ctypes.c_double),
                 ("tau_f", ctypes.c_double), ("tau_g", ctypes.c_double),
-                ("n", ctypes.c_long * 3), ("open_end", ctypes.c_int * 3)]
+                ("n", ctypes.c_long * 3), ("open_end", ctypes.c_int * 3),
+                ("energy_fix", ctypes.c_int)]
 
 
 _lib = None
@@ -90,10 +91,13 @@ class OracleLBM:
     step; tau in lattice units), or the time step of the finite-difference
     form of Sec. III (grid step 1, speeds xi_i = r e_i; tau_f and tau_g then
     in the units of dt).
+
+    ``energy_fix``: the energy-conserving collision for tau_f != tau_g (a
+    mode beyond the paper; see energy_fix_kappa in the C source).
     """
 
     def __init__(self, dim, gamma, tau_f, tau_g, nx, ny, nz=1,
-                 open_end=(False, False, False), delta=None, dt=None):
+                 open_end=(False, False, False), delta=None, dt=None, energy_fix=False):
         self.lat = lattice(dim)
         self.dim = dim
         self.delta = delta_from_gamma(gamma, dim) if delta is None else delta
@@ -113,6 +117,7 @@ class OracleLBM:
         for k in range(3):
             m.n[k] = self.shape[k]
             m.open_end[k] = 1 if open_end[k] else 0
+        m.energy_fix = 1 if energy_fix else 0
         self._m = m
         self.ncells = nx * ny * self.shape[2]
         self.g = np.zeros((self.ncells, self.lat.Q))
