@@ -101,6 +101,24 @@ int lbm_create_ex(int dim, int velocity_set, double gamma, double tau_f,
                   double tau_g, int64_t nx, int64_t ny, int64_t nz,
                   uint32_t bc, int precision, lbm_handle *out);
 
+/* Collision of a solve.
+ * PAPER: the BGK collision of Secs. II-III, g toward F with tau_f and h
+ *   toward (delta/2) T F with tau_g.  With tau_f != tau_g it does not
+ *   conserve total energy: a cell's energy changes by (a_f - a_g)
+ *   (E_tr^eq - E_tr) per step (a = 1/tau per lattice step, dt/tau per
+ *   finite-difference step; E_tr = sum xi^2 g / 2, E_tr^eq = rho (u^2 +
+ *   D T) / 2).
+ * ENERGY_CONSERVING: not in the paper.  h relaxes toward ((delta/2) T +
+ *   kappa) F with kappa rho = (1 - a_f / a_g)(E_tr^eq - E_tr), which
+ *   conserves total energy exactly for any tau_f, tau_g and is the paper's
+ *   collision when tau_f = tau_g.  Mass, momentum and g's relaxation are
+ *   unchanged. */
+enum lbm_collision { LBM_COLLISION_PAPER = 0, LBM_COLLISION_ENERGY_CONSERVING = 1 };
+
+/* Select the collision (default PAPER).  Must precede lbm_init_fields:
+ * ESTATE once the handle holds a state; EINVAL for other modes. */
+int lbm_set_collision(lbm_handle h, int mode);
+
 /* Create a solve that advances by the finite-difference form of Sec. III
  * instead of lattice streaming: explicit Euler in time with step dt,
  *   g_i(t+dt) = g_i - dt xi_i . grad g_i - (dt/tau_f) (g_i - F_i),
@@ -189,6 +207,7 @@ typedef struct {
     size_t device_bytes;    /* device memory held by the handle */
     int scheme;             /* 0: lattice streaming, 1: finite differences */
     double dt;              /* finite-difference time step (0 for lattice) */
+    int collision;          /* enum lbm_collision */
 } lbm_info;
 int lbm_get_info(lbm_handle h, lbm_info *info);
 

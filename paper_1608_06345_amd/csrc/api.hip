@@ -85,7 +85,8 @@ lbm::StepArgs step_args(const lbm_solver* h, const void* src, void* dst, bool st
     a.nxy = (int32_t)(h->nx * h->ny);
     a.open_end = (h->bc & 3u) | (((h->bc >> 2) & 3u) << 1) | (((h->bc >> 4) & 3u) << 2);
     a.stream = stream ? 1 : 0;
-    a.ph = lbm::physics_of(h->dim, h->delta, h->tau_f, h->tau_g, h->scheme ? h->dt : 0.0);
+    a.ph = lbm::physics_of(h->dim, h->delta, h->tau_f, h->tau_g, h->scheme ? h->dt : 0.0,
+                           h->collision == LBM_COLLISION_ENERGY_CONSERVING);
     return a;
 }
 
@@ -298,6 +299,17 @@ int lbm_set_variant(lbm_handle h, int variant) {
     }
 }
 
+int lbm_set_collision(lbm_handle h, int mode) {
+    if (!h) return LBM_EINVAL;
+    if (mode != LBM_COLLISION_PAPER && mode != LBM_COLLISION_ENERGY_CONSERVING)
+        return LBM_EINVAL;
+    // the lattice scheme stores post-collision states: a state collided in
+    // one mode cannot continue in the other
+    if (h->have_state) return LBM_ESTATE;
+    h->collision = mode;
+    return LBM_OK;
+}
+
 int lbm_synchronize(lbm_handle h) {
     if (!h) return LBM_EINVAL;
     LBM_HIP(hipStreamSynchronize(h->stream));
@@ -420,6 +432,7 @@ int lbm_get_info(lbm_handle h, lbm_info* info) {
     info->device_bytes = h->device_bytes;
     info->scheme = h->scheme;
     info->dt = h->dt;
+    info->collision = h->collision;
     return LBM_OK;
 }
 

@@ -142,7 +142,8 @@ std::once_flag g_once;
 
 }  // namespace
 
-Physics physics_of(int dim, double delta, double tau_f, double tau_g, double dt) {
+Physics physics_of(int dim, double delta, double tau_f, double tau_g, double dt,
+                   bool energy_fix) {
     const LatticeTables& t = lattice_tables(dim);
     Physics ph;
     std::memset(&ph, 0, sizeof(ph));
@@ -153,6 +154,9 @@ Physics physics_of(int dim, double delta, double tau_f, double tau_g, double dt)
     ph.omega_g = step / tau_g;
     ph.fd_cs = dt > 0.0 ? dt * t.r / 6.0 : 0.0;
     ph.fd_csf = (float)ph.fd_cs;
+    // rates a_f / a_g = tau_g / tau_f in both forms
+    ph.ec = energy_fix ? 1.0 - tau_g / tau_f : 0.0;
+    ph.ecf = (float)ph.ec;
     ph.half_delta = 0.5 * delta;
     ph.inv_dof = 1.0 / (dim + delta);
     ph.r = t.r;

@@ -41,6 +41,8 @@ struct Physics {
     float inv_wf[10];         // 1 / w (scaling of half-precision storage)
     double fd_cs;             // finite differences: dt r / 6 (0 for the lattice scheme)
     float fd_csf;             // the same, rounded to float
+    double ec;                // energy-conserving collision: 1 - tau_g / tau_f, else 0
+    float ecf;                // the same, rounded to float
 };
 
 // Arguments of the fused step kernel (passed by value in the kernarg
@@ -63,7 +65,9 @@ struct StepArgs {
 
 // Collision parameters of a solve (lattice.cpp).  dt > 0 selects the
 // finite-difference form: relaxation rates dt / tau, convection scale dt r / 6.
-Physics physics_of(int dim, double delta, double tau_f, double tau_g, double dt = 0.0);
+// energy_fix selects the energy-conserving collision (see collide_*).
+Physics physics_of(int dim, double delta, double tau_f, double tau_g, double dt = 0.0,
+                   bool energy_fix = false);
 
 // Arguments of the readout kernel (moments and conservation partials).
 struct ReadArgs {
@@ -132,6 +136,7 @@ struct lbm_solver {
     bool initial;         // buf[cur ^ 1] holds S_0 itself (no step yet)
     int64_t steps;
     int scheme;           // 0: lattice (collide, stream), 1: finite differences
+    int collision;        // LBM_COLLISION_PAPER or LBM_COLLISION_ENERGY_CONSERVING
     double dt;            // finite-difference time step (grid step 1, speeds r e)
     double* partials;     // readout block partials
     double* totals;       // [D + 2] final totals (device)

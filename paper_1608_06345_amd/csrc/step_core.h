@@ -189,6 +189,14 @@ __host__ __device__ constexpr int l1_of(Vel v) {
     return (v.x < 0 ? -v.x : v.x) + (v.y < 0 ? -v.y : v.y) + (v.z < 0 ? -v.z : v.z);
 }
 
+// Energy-conserving collision coefficient 1 - tau_g / tau_f (0 when off), in T.
+template <typename T>
+__device__ __forceinline__ T ec_coef(const Physics& ph);
+template <>
+__device__ __forceinline__ double ec_coef<double>(const Physics& ph) { return ph.ec; }
+template <>
+__device__ __forceinline__ float ec_coef<float>(const Physics& ph) { return ph.ecf; }
+
 // Convection scale dt r / 6 of the finite-difference form, in T.
 template <typename T>
 __device__ __forceinline__ T fd_scale(const Physics& ph);
@@ -364,6 +372,28 @@ __device__ __forceinline__ void fill_row_offsets(RowOffsets<T>& o, int x, int y,
     o.row = (uint32_t)(y * nx + z * nxy) * (uint32_t)sizeof(T);
 }
 
+// Energy-conserving collision (a mode beyond the paper).  With rates a_f,
+// a_g the BGK step changes a cell's total energy by (a_f - a_g)
+// (E_tr^eq - E_tr), E_tr = sum xi^2 g / 2 and E_tr^eq = rho (u^2 + D T) / 2,
+// because sum h relaxes at the other rate toward the complement.  h relaxed
+// toward ((delta/2) T + kappa) F with
+//   kappa rho = (1 - a_f / a_g) (E_tr^eq - E_tr)
+// conserves energy exactly.  Returns kappa rho; a signed zero when the mode
+// is off (coefficient 0), which leaves every target bit-identical.  In
+// deviation storage E_tr^eq - E_tr = (r^2 / 2)(want_e - se), both sums over
+// deviations.
+template <int D, typename T, bool DEV>
+__device__ __forceinline__ T energy_fix_kr(const Physics& ph, T rho,
+                                           const Equilibrium<D, T, DEV>& eq, T want_e, T se) {
+    T diff;
+    if constexpr (DEV) {
+        diff = T(0.5) * eq.r2 * (want_e - se);
+    } else {
+        diff = T(0.5) * (rho * (eq.U + T(D) * (T(1) + eq.t)) - eq.r2 * se);
+    }
+    return ec_coef<T>(ph) * diff;
+}
+
 // Collision of one cell, one lane holding all 2Q populations (g and h).
 template <int D, class P, bool FD = false>
 __device__ __forceinline__ void collide_lane(typename P::T* g, typename P::T* h,
@@ -380,13 +410,15 @@ __device__ __forceinline__ void collide_lane(typename P::T* g, typename P::T* h,
     const T hd = T(ph.half_delta);
     const T hdT = hd * (T(1) + t);
     // BGK targets: F for g; (delta/2) T F for h (shifted by the rest state in
-    // deviation storage); exact target moments for the correction
-    const T beta_g = DEV ? drho : T(0);
-    const T beta_h = DEV ? hdT * drho + hd * t : T(0);
+    // deviation storage), plus kappa F in the energy-conserving mode; exact
+    // target moments for the correction
     const T want_e = (rho * eq.U + T(D) * (drho + rho * t)) / eq.r2;
+    const T kr = energy_fix_kr<D, T, DEV>(ph, rho, eq, want_e, se);
+    const T beta_g = DEV ? drho : T(0);
+    const T beta_h = DEV ? hdT * drho + hd * t + kr : T(0);
     relax<D, T, DEV, FD>(g, eq, ph, rho, beta_g, T(ph.omega_f), drho, sj, want_e, T(1));
-    relax<D, T, DEV, FD>(h, eq, ph, hdT * rho, beta_h, T(ph.omega_g), hd * (drho + rho * t), sj,
-                     T(0), T(0));
+    relax<D, T, DEV, FD>(h, eq, ph, hdT * rho + kr, beta_h, T(ph.omega_g),
+                         hd * (drho + rho * t) + kr, sj, T(0), T(0));
 }
 
 // Collision of one cell in the split layout: lane l < 32 holds the g
@@ -418,10 +450,11 @@ __device__ __forceinline__ void collide_split(typename P::T* p, int role, const 
     eq.setup(u, t, T(ph.r));
     const T hd = T(ph.half_delta);
     const T hdT = hd * (T(1) + t);
-    const T arho = role ? hdT * rho : rho;
-    const T beta = DEV ? (role ? hdT * drho + hd * t : drho) : T(0);
     const T want_e = (rho * eq.U + T(D) * (drho + rho * t)) / eq.r2;
-    const T want_m = role ? hd * (drho + rho * t) : drho;
+    const T kr = energy_fix_kr<D, T, DEV>(ph, rho, eq, want_e, ge);
+    const T arho = role ? hdT * rho + kr : rho;
+    const T beta = DEV ? (role ? hdT * drho + hd * t + kr : drho) : T(0);
+    const T want_m = role ? hd * (drho + rho * t) + kr : drho;
     relax<D, T, DEV, FD>(p, eq, ph, arho, beta, role ? T(ph.omega_g) : T(ph.omega_f), want_m, gj,
                      want_e, role ? T(0) : T(1));
 }

@@ -29,6 +29,7 @@ LBM_D2Q37, LBM_D3Q107 = 37, 107
 LBM_BC_PERIODIC, LBM_BC_ZERO_GRADIENT = 0, 1
 LBM_FP64, LBM_FP32_DEV, LBM_FP16_SCALED = 0, 1, 2
 LBM_VARIANT_AUTO, LBM_VARIANT_LANE, LBM_VARIANT_SPLIT = 0, 1, 2
+LBM_COLLISION_PAPER, LBM_COLLISION_ENERGY_CONSERVING = 0, 1
 
 
 def LBM_BC(bx, by, bz=0):
@@ -54,7 +55,7 @@ class _Info(ctypes.Structure):
                 ("gamma", ctypes.c_double), ("delta", ctypes.c_double),
                 ("tau_f", ctypes.c_double), ("tau_g", ctypes.c_double), ("r", ctypes.c_double),
                 ("steps", ctypes.c_int64), ("device_bytes", ctypes.c_size_t),
-                ("scheme", ctypes.c_int), ("dt", ctypes.c_double)]
+                ("scheme", ctypes.c_int), ("dt", ctypes.c_double), ("collision", ctypes.c_int)]
 
 
 class lbm_request(ctypes.Structure):
@@ -85,6 +86,7 @@ def _load():
         "lbm_destroy": [vp],
         "lbm_set_stream": [vp, vp],
         "lbm_set_variant": [vp, i32],
+        "lbm_set_collision": [vp, i32],
         "lbm_synchronize": [vp],
         "lbm_init_fields": [vp, dp, dp, dp],
         "lbm_init_fields_dev": [vp, vp, vp, vp],
@@ -213,6 +215,10 @@ def lbm_set_variant(h, variant):
     _check(_lib.lbm_set_variant(h, int(variant)), "lbm_set_variant")
 
 
+def lbm_set_collision(h, mode):
+    _check(_lib.lbm_set_collision(h, int(mode)), "lbm_set_collision")
+
+
 def lbm_synchronize(h):
     _check(_lib.lbm_synchronize(h), "lbm_synchronize")
 
@@ -293,12 +299,14 @@ class Solver:
     else by lattice streaming."""
 
     def __init__(self, dim, gamma, tau_f, tau_g, nx, ny, nz=1, bc=0, precision=LBM_FP64,
-                 dt=None):
+                 dt=None, collision=LBM_COLLISION_PAPER):
         vs = LBM_D2Q37 if dim == 2 else LBM_D3Q107
         if dt is None:
             self.h = lbm_create_ex(dim, vs, gamma, tau_f, tau_g, nx, ny, nz, bc, precision)
         else:
             self.h = lbm_create_fd(dim, vs, gamma, tau_f, tau_g, dt, nx, ny, nz, bc, precision)
+        if collision != LBM_COLLISION_PAPER:
+            lbm_set_collision(self.h, collision)
         self.dim = dim
         self.ncells = nx * ny * nz
 

@@ -85,6 +85,7 @@ def test_invalid_precision_and_null_handles():
     assert lib.lbm_step(None, 1) == lbm.LBM_EINVAL
     assert lib.lbm_destroy(None) == lbm.LBM_OK
     assert lib.lbm_set_variant(None, 0) == lbm.LBM_EINVAL
+    assert lib.lbm_set_collision(None, 1) == lbm.LBM_EINVAL
     assert lbm.lbm_strerror(lbm.LBM_ENONFINITE).startswith("non-finite")
     assert lbm.lbm_strerror(12345) == "unknown status"
 
