@@ -162,7 +162,18 @@ int lbm_set_stream(lbm_handle h, void *stream);
  * lane pair holds them, g in lane l and h in lane l + 32 of the wave.  AUTO
  * (the default) takes LANE for D2Q37 and SPLIT for D3Q107, whose 214
  * populations do not fit one lane's registers.  EINVAL for other values. */
-enum lbm_variant { LBM_VARIANT_AUTO = 0, LBM_VARIANT_LANE = 1, LBM_VARIANT_SPLIT = 2 };
+enum lbm_variant {
+    LBM_VARIANT_AUTO = 0,
+    LBM_VARIANT_LANE = 1,
+    LBM_VARIANT_SPLIT = 2,
+    LBM_VARIANT_TWO_PASS = 3
+};
+/* For solves made with lbm_create_fd: TWO_PASS runs the finite-difference
+ * step in two passes -- a moments pass, then updates of chunks of
+ * populations, which keeps each chunk's neighbour rows in cache; LANE and
+ * SPLIT run it as one fused kernel in the named layout; AUTO takes TWO_PASS
+ * except for D2Q37 in FP64, where the fused kernel is faster.  TWO_PASS is
+ * EINVAL for lattice-streaming solves. */
 int lbm_set_variant(lbm_handle h, int variant);
 
 /* Block until the handle's stream is idle. */

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["kernels.hip", "api.hip", "pool.hip", "lattice.cpp"]
+SOURCES = ["kernels.hip", "fd.hip", "api.hip", "pool.hip", "lattice.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

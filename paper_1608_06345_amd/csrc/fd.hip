@@ -1,0 +1,378 @@
+// The finite-difference form of Sec. III in two passes per step.
+//
+// The fused kernel (k_fd_step in kernels.hip) reads each population's
+// upwind neighbours from cache.  At D3Q107 the rows around the cells in
+// flight on one XCD, over all 214 planes, exceed its L2, so neighbour rows
+// are fetched from HBM again and again.  Here a step is split:
+//
+//   moments pass  one lane per cell streams the 2Q centre values once,
+//                 keeping only running sums, and writes a per-cell record:
+//                 the macroscopic state, kappa rho of the energy-conserving
+//                 collision, and (FP32 deviation storage) the residuals of
+//                 the exact-moment correction of the targets;
+//   update passes one lane per cell, a chunk of populations per launch:
+//                 the chunk's targets from the record, relaxation with
+//                 rates dt / tau and the upwind convection, whose neighbour
+//                 rows -- a chunk's planes only -- stay in the L2.
+//
+// The arithmetic is that of the fused kernel: the same equilibrium, the
+// same target sums for the correction (accumulated in the same order), the
+// same relaxation and convection terms.
+#include <type_traits>
+
+#include "lbm_internal.h"
+#include "step_core.h"
+
+namespace lbm {
+namespace {
+
+using namespace core;
+
+// Record fields, each a plane of N values in the arithmetic type:
+//   0 drho (deviation storage) or rho; 1..D u; D+1 t = T - 1; D+2 kappa rho;
+//   deviation storage only: D+3 dm_g, D+4 .. 2D+3 dj_g, 2D+4 de_g, 2D+5 dm_h.
+template <int D, bool DEV>
+constexpr int kRecFields = DEV ? 2 * D + 6 : D + 3;
+
+// Population chunks of the update passes: the rest and axis populations
+// (which take the correction) with the first pairs, then 14 at a time.
+template <int D>
+constexpr int kChunk0 = D == 2 ? 13 : 15;
+constexpr int kChunkW = 14;
+template <int D>
+constexpr int chunk_count() {
+    constexpr int Q = VelSet<D>::Q;
+    return 1 + (Q - kChunk0<D> + kChunkW - 1) / kChunkW;
+}
+template <int D>
+constexpr int chunk_begin(int c) { return c == 0 ? 0 : kChunk0<D> + (c - 1) * kChunkW; }
+template <int D>
+constexpr int chunk_end(int c) {
+    constexpr int Q = VelSet<D>::Q;
+    const int e = kChunk0<D> + c * kChunkW;
+    return c == 0 ? kChunk0<D> : (e < Q ? e : Q);
+}
+
+// Uncorrected targets' moment sums and the residuals of the exact-moment
+// correction (as relax<…, DEV> forms them: per +- pair, group by group,
+// then the rest population).
+template <int D, typename T>
+__device__ __forceinline__ void target_residuals(const Equilibrium<D, T, true>& eq,
+                                                 const Physics& a, T arho, T beta, T want_m,
+                                                 const T* want_j, T want_e, T je_on, T& dm,
+                                                 T* dj, T& de) {
+    constexpr VelSet<D> V = kVelSet<D>;
+    constexpr int G = VelSet<D>::G;
+    T sm = 0, sjx = 0, sjy = 0, sjz = 0, se = 0;
+    static_for<1, G>([&](auto Gi) {
+        constexpr int g = decltype(Gi)::value;
+        T A0, A1, A2;
+        eq.template coef<V.qn[g]>(A0, A1, A2);
+        const T w = weight<T>(a, g);
+        constexpr int first = group_start<D>(g);
+        static_for<0, V.count[g] / 2>([&](auto Pi) {
+            constexpr int i = first + 2 * decltype(Pi)::value;
+            constexpr Vel v = V.v[i];
+            const T c = eq.template dot<v.x, v.y, v.z>();
+            const T c2 = c * c;
+            const T even = A0 + c2 * (A2 + c2 * T(1.0 / 24.0));
+            const T odd = c * (A1 + c2 * T(1.0 / 6.0));
+            const T tp = w * (arho * (even + odd) + beta);
+            const T tm = w * (arho * (even - odd) + beta);
+            const T sum = tp + tm;
+            const T dif = tp - tm;
+            sm += sum;
+            if constexpr (v.x != 0) sjx += T(v.x) * dif;
+            if constexpr (v.y != 0) sjy += T(v.y) * dif;
+            if constexpr (D == 3 && v.z != 0) sjz += T(v.z) * dif;
+            se += T(V.qn[g]) * sum;
+        });
+    });
+    T A0, A1, A2;
+    eq.template coef<0>(A0, A1, A2);
+    sm += weight<T>(a, 0) * (arho * A0 + beta);
+    dm = want_m - sm;
+    de = je_on * (want_e - se);
+    dj[0] = je_on * (want_j[0] - sjx);
+    dj[1] = je_on * (want_j[1] - sjy);
+    if constexpr (D == 3) dj[2] = je_on * (want_j[2] - sjz);
+}
+
+template <int D, class P>
+__global__ __launch_bounds__(256) void k_fd_moments(const void* __restrict__ src_v,
+                                                    typename P::T* __restrict__ rec, int64_t N,
+                                                    const Physics ph) {
+    using T = typename P::T;
+    using S = typename P::S;
+    constexpr bool DEV = P::kDev;
+    constexpr VelSet<D> V = kVelSet<D>;
+    constexpr int Q = VelSet<D>::Q;
+    const int64_t cell = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (cell >= N) return;  // lanes are independent here
+    const S* src = static_cast<const S*>(src_v);
+    // running sums over the centre values (moment_sums, streamed)
+    T s0 = 0, sx = 0, sy = 0, sz = 0, se = 0, sh = 0;
+    static_for<0, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr Vel v = V.v[i];
+        const T x = from_store<P>(src[(size_t)(2 * i) * N + cell], ph, v.group);
+        const T y = from_store<P>(src[(size_t)(2 * i + 1) * N + cell], ph, v.group);
+        s0 += x;
+        if constexpr (v.x != 0) sx += T(v.x) * x;
+        if constexpr (v.y != 0) sy += T(v.y) * x;
+        if constexpr (D == 3 && v.z != 0) sz += T(v.z) * x;
+        if constexpr (V.qn[v.group] != 0) se += T(V.qn[v.group]) * x;
+        sh += y;
+    });
+    T sj[3] = {sx, sy, sz};
+    T rho, drho, u[3] = {0, 0, 0}, t;
+    macro<D, T, DEV>(s0, sj, se, sh, T(ph.r), ph.inv_dof, ph.half_delta, rho, drho, u, t);
+    Equilibrium<D, T, DEV> eq;
+    eq.setup(u, t, T(ph.r));
+    const T want_e = (rho * eq.U + T(D) * (drho + rho * t)) / eq.r2;
+    const T kr = energy_fix_kr<D, T, DEV>(ph, rho, eq, want_e, se);
+    rec[cell] = DEV ? drho : rho;
+#pragma unroll
+    for (int k = 0; k < D; ++k) rec[(size_t)(1 + k) * N + cell] = u[k];
+    rec[(size_t)(D + 1) * N + cell] = t;
+    rec[(size_t)(D + 2) * N + cell] = kr;
+    if constexpr (DEV) {
+        const T hd = T(ph.half_delta);
+        const T hdT = hd * (T(1) + t);
+        T dm, dj[3] = {0, 0, 0}, de;
+        target_residuals<D, T>(eq, ph, rho, drho, drho, sj, want_e, T(1), dm, dj, de);
+        rec[(size_t)(D + 3) * N + cell] = dm;
+#pragma unroll
+        for (int k = 0; k < D; ++k) rec[(size_t)(D + 4 + k) * N + cell] = dj[k];
+        rec[(size_t)(2 * D + 4) * N + cell] = de;
+        T dmh, djh[3] = {0, 0, 0}, deh;
+        target_residuals<D, T>(eq, ph, hdT * rho + kr, hdT * drho + hd * t + kr,
+                               hd * (drho + rho * t) + kr, sj, T(0), T(0), dmh, djh, deh);
+        rec[(size_t)(2 * D + 5) * N + cell] = dmh;
+    }
+}
+
+// Update of populations [C0, C1) of every cell: target, relaxation with the
+// convection centre term, neighbour terms, store (see relax and
+// convect_store_* for the same steps in the fused kernel).
+template <int D, class P, int C0, int C1>
+__global__ __launch_bounds__(256) void k_fd_update(const void* __restrict__ src_v,
+                                                   void* __restrict__ dst_v,
+                                                   const typename P::T* __restrict__ rec,
+                                                   const StepArgs a) {
+    using T = typename P::T;
+    using S = typename P::S;
+    constexpr bool DEV = P::kDev;
+    constexpr VelSet<D> V = kVelSet<D>;
+    const int64_t N = a.N;
+    // Sweep order (2.5D blocking).  A tile is 256 cells of one x-row.  The
+    // rows are cut into y sub-bands of fd_yb rows, dealt to the XCDs round-
+    // robin (sub-band s to XCD s % 8, which is workgroup b % 8); an XCD sweeps
+    // each of its sub-bands x-chunk (fd_w tiles) by x-chunk, and within a
+    // chunk z-slab by z-slab, row by row.  The planes a stencil reads at
+    // y +- 1, 2 and z +- 1, 2 were then fetched by the same XCD within the
+    // last few sub-band slabs, which the host sizes to stay in its L2.
+    const int b = (int)blockIdx.x;
+    const int W = a.fd_w, YB = a.fd_yb;
+    const int chunks = (a.tiles_per_row + W - 1) / W;
+    const int per_chunk = W * YB * a.nz;
+    const int per_sub = chunks * per_chunk;
+    const int j = b >> 3;
+    const int round = j / per_sub;
+    const int in_sub = j - round * per_sub;
+    const int chunk = in_sub / per_chunk;
+    const int in_chunk = in_sub - chunk * per_chunk;
+    const int cz = in_chunk / (YB * W);
+    const int in_slab = in_chunk - cz * (YB * W);
+    const int cy = (round * 8 + (b & 7)) * YB + in_slab / W;
+    const int xt = chunk * W + in_slab % W;
+    const int cx = xt * 256 + (int)threadIdx.x;
+    if (xt >= a.tiles_per_row || cy >= a.ny || cx >= a.nx) return;
+    const int64_t cell = (int64_t)cx + (int64_t)a.nx * cy + (int64_t)a.nxy * cz;
+    const Physics& ph = a.ph;
+    PullTable<D> pt;  // pt.src for shift e gives the cell at x - e (wrapped or clamped)
+    pt.fill(cx, cy, cz, a.nx, a.ny, a.nz, a.nxy, a.open_end, true);
+    const S* src = static_cast<const S*>(src_v);
+    S* dst = static_cast<S*>(dst_v);
+
+    const T m0 = rec[cell];
+    T u[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < D; ++k) u[k] = rec[(size_t)(1 + k) * N + cell];
+    const T t = rec[(size_t)(D + 1) * N + cell];
+    const T kr = rec[(size_t)(D + 2) * N + cell];
+    const T rho = DEV ? T(1) + m0 : m0;
+    const T drho = DEV ? m0 : m0 - T(1);
+    Equilibrium<D, T, DEV> eq;
+    eq.setup(u, t, T(ph.r));
+    const T hd = T(ph.half_delta);
+    const T hdT = hd * (T(1) + t);
+    const T arho_h = hdT * rho + kr;
+    const T beta_g = DEV ? drho : T(0);
+    const T beta_h = DEV ? hdT * drho + hd * t + kr : T(0);
+    // correction residuals: only the first chunk holds the rest and axis
+    // populations that take them
+    T dm = 0, de = 0, dmh = 0, dj[3] = {0, 0, 0};
+    if constexpr (DEV && C0 == 0) {
+        dm = rec[(size_t)(D + 3) * N + cell];
+#pragma unroll
+        for (int k = 0; k < D; ++k) dj[k] = rec[(size_t)(D + 4 + k) * N + cell];
+        de = rec[(size_t)(2 * D + 4) * N + cell];
+        dmh = rec[(size_t)(2 * D + 5) * N + cell];
+    }
+    const T omf = T(ph.omega_f), omg = T(ph.omega_g);
+    const T cs = fd_scale<T>(ph);
+    // offset of the neighbour x + d along axis A of this cell
+    auto nbr = [&](auto Ax, auto Dd) {
+        constexpr int ax = decltype(Ax)::value;
+        constexpr int d = decltype(Dd)::value;
+        int o = ax == 0 ? pt.x[3 - d] : pt.x[3];
+        o += ax == 1 ? pt.y[3 - d] : pt.y[3];
+        if constexpr (D == 3) o += ax == 2 ? pt.z[3 - d] : pt.z[3];
+        return o;
+    };
+    static_for<C0, C1>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr Vel v = V.v[i];
+        constexpr int g = v.group;
+        // target (uncorrected): w (arho P~(c) + beta), +- pair arithmetic
+        T A0, A1, A2;
+        eq.template coef<V.qn[g]>(A0, A1, A2);
+        const T w = weight<T>(ph, g);
+        T pg;  // P~ for this population
+        if constexpr (i == 0) {
+            pg = A0;
+        } else {
+            constexpr int first = (i - group_start<D>(g)) % 2 == 0 ? i : i - 1;
+            constexpr Vel vf = V.v[first];
+            const T c = eq.template dot<vf.x, vf.y, vf.z>();
+            const T c2 = c * c;
+            const T even = A0 + c2 * (A2 + c2 * T(1.0 / 24.0));
+            const T odd = c * (A1 + c2 * T(1.0 / 6.0));
+            pg = i == first ? even + odd : even - odd;
+        }
+        T tg = w * (rho * pg + beta_g);
+        T th = w * (arho_h * pg + beta_h);
+        if constexpr (DEV && i == 0) {
+            tg += dm - de;
+            th += dmh;
+        }
+        if constexpr (DEV && i >= 1 && i <= 2 * D) {
+            constexpr int axis = v.x != 0 ? 0 : (v.y != 0 ? 1 : 2);
+            constexpr int s = (v.x + v.y + v.z) > 0 ? 1 : -1;
+            const T half = T(0.5) * dj[axis];
+            tg += s > 0 ? de * T(1.0 / (2 * D)) + half : de * T(1.0 / (2 * D)) - half;
+        }
+        // relaxation with the convection centre term (relax<…, FD>)
+        const size_t pg_off = (size_t)(2 * i) * N, ph_off = pg_off + N;
+        T xg = from_store<P>(src[pg_off + cell], ph, g);
+        T xh = from_store<P>(src[ph_off + cell], ph, g);
+        if constexpr (l1_of(v) != 0) {
+            const T kc = T(3 * l1_of(v)) * cs;
+            xg = (xg - kc * xg) + omf * (tg - xg);
+            xh = (xh - kc * xh) + omg * (th - xh);
+        } else {
+            xg = xg + omf * (tg - xg);
+            xh = xh + omg * (th - xh);
+        }
+        // neighbour terms (fd_neighbours)
+        T nbg = T(0), nbh = T(0);
+        static_for<0, D>([&](auto A) {
+            constexpr int ax = decltype(A)::value;
+            constexpr int e = ax == 0 ? v.x : (ax == 1 ? v.y : v.z);
+            if constexpr (e != 0) {
+                constexpr int s = e > 0 ? 1 : -1;
+                constexpr int m = e > 0 ? e : -e;
+                const int o2 = nbr(A, std::integral_constant<int, -2 * s>{});
+                const int o1 = nbr(A, std::integral_constant<int, -s>{});
+                const int oa = nbr(A, std::integral_constant<int, s>{});
+                nbg += T(m) * ((from_store<P>(src[pg_off + o2], ph, g) -
+                                T(6) * from_store<P>(src[pg_off + o1], ph, g)) +
+                               T(2) * from_store<P>(src[pg_off + oa], ph, g));
+                nbh += T(m) * ((from_store<P>(src[ph_off + o2], ph, g) -
+                                T(6) * from_store<P>(src[ph_off + o1], ph, g)) +
+                               T(2) * from_store<P>(src[ph_off + oa], ph, g));
+            }
+        });
+        store_at(reinterpret_cast<char*>(dst + pg_off), (uint32_t)(cell * sizeof(S)),
+                 to_store<P>(xg - cs * nbg, ph, g));
+        store_at(reinterpret_cast<char*>(dst + ph_off), (uint32_t)(cell * sizeof(S)),
+                 to_store<P>(xh - cs * nbh, ph, g));
+    });
+}
+
+template <int D, class P, int C>
+hipError_t launch_chunks(const StepArgs& a, const typename P::T* rec, int grid, hipStream_t s) {
+    if constexpr (C == chunk_count<D>()) {
+        return hipSuccess;
+    } else {
+        hipError_t e = launch_kernel(&k_fd_update<D, P, chunk_begin<D>(C), chunk_end<D>(C)>,
+                                     dim3(grid), dim3(256), s, a.src, a.dst, rec, a);
+        if (e != hipSuccess) return e;
+        return launch_chunks<D, P, C + 1>(a, rec, grid, s);
+    }
+}
+
+// Bytes of the planes that one update chunk's stencils keep live: the
+// reuse window (the slabs z-2 .. z+2 of a sub-band's x-chunk in 3D, the rows
+// y-2 .. y+2 of an x-chunk in 2D) is held within this much of an XCD's L2.
+constexpr int64_t kFdWindowBytes = 2 << 20;
+
+template <int D, class P>
+hipError_t fd_two_pass_impl(const StepArgs& a0, void* rec_v, hipStream_t s) {
+    using T = typename P::T;
+    StepArgs a = a0;
+    T* rec = static_cast<T*>(rec_v);
+    const int tiles = (int)((a.N + 255) / 256);
+    hipError_t e = launch_kernel(&k_fd_moments<D, P>, dim3(tiles), dim3(256), s, a.src, rec, a.N,
+                                 a.ph);
+    if (e != hipSuccess) return e;
+    // one x-row tile of one chunk's planes (at most 14 populations, g and h)
+    const int64_t tile_bytes = 256LL * 2 * kChunkW * (int64_t)sizeof(typename P::S);
+    a.tiles_per_row = (a.nx + 255) / 256;
+    int64_t budget = kFdWindowBytes / (5 * tile_bytes);  // tiles in a reuse window
+    if (budget < 1) budget = 1;
+    if (D == 3) {
+        // x-chunks of whole rows when they fit, sub-bands of YB rows: the
+        // window is 5 slabs of YB x W tiles
+        a.fd_w = (int)(a.tiles_per_row < budget ? a.tiles_per_row : budget);
+        // the tallest sub-band within the window that splits y into k
+        // rounds of eight (every XCD takes the same number of sub-bands)
+        const int64_t max_yb = budget / a.fd_w;
+        int k = 1;
+        while ((a.ny + 8 * k - 1) / (8 * k) > max_yb && 8 * k < a.ny) ++k;
+        a.fd_yb = (a.ny + 8 * k - 1) / (8 * k);
+    } else {
+        // one sub-band per XCD; the window is 5 rows of a W-tile chunk
+        a.fd_w = (int)(a.tiles_per_row < budget ? a.tiles_per_row : budget);
+        a.fd_yb = (a.ny + 7) / 8;
+    }
+    const int chunks = (a.tiles_per_row + a.fd_w - 1) / a.fd_w;
+    const int subs = (a.ny + a.fd_yb - 1) / a.fd_yb;
+    const int rounds = (subs + 7) / 8;
+    const int64_t grid = 8LL * rounds * chunks * a.fd_w * a.fd_yb * a.nz;
+    if (grid > 0x7fffffff) return hipErrorInvalidValue;
+    return launch_chunks<D, P, 0>(a, rec, (int)grid, s);
+}
+
+}  // namespace
+
+size_t fd_record_bytes(int dim, int precision, int64_t N) {
+    const bool dev = precision != LBM_FP64;
+    const int fields = dim == 2 ? (dev ? kRecFields<2, true> : kRecFields<2, false>)
+                                : (dev ? kRecFields<3, true> : kRecFields<3, false>);
+    return (size_t)fields * (size_t)N * (precision == LBM_FP64 ? 8 : 4);
+}
+
+hipError_t launch_fd_two_pass(int dim, int precision, const StepArgs& a, void* record,
+                              hipStream_t s) {
+    if (precision == LBM_FP64)
+        return dim == 2 ? fd_two_pass_impl<2, F64>(a, record, s)
+                        : fd_two_pass_impl<3, F64>(a, record, s);
+    if (precision == LBM_FP32_DEV)
+        return dim == 2 ? fd_two_pass_impl<2, F32Dev>(a, record, s)
+                        : fd_two_pass_impl<3, F32Dev>(a, record, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace lbm

@@ -60,6 +60,8 @@ struct StepArgs {
     int32_t items;        // row segments in the grid
     int32_t tiles_per_row;  // workgroups (four segments each) per row
     int32_t xcd_rows;     // 1: each XCD serves whole rows (see kernels.hip)
+    int32_t fd_w;         // finite-difference update sweep: tiles per x-chunk
+    int32_t fd_yb;        // finite-difference update sweep: rows per y sub-band
     Physics ph;
 };
 
@@ -112,6 +114,12 @@ hipError_t launch_step(int dim, int precision, bool split, const StepArgs& a,
 // fields of a copy of `a`.
 hipError_t launch_fd_step(int dim, int precision, bool split, const StepArgs& a,
                           hipStream_t s);
+// The same step in two passes (fd.hip): a moments pass writing a per-cell
+// record, then update passes over chunks of populations.  FP64 and FP32
+// deviation storage.
+size_t fd_record_bytes(int dim, int precision, int64_t N);
+hipError_t launch_fd_two_pass(int dim, int precision, const StepArgs& a, void* record,
+                              hipStream_t s);
 int step_block_cells(int dim, int precision, bool split);
 hipError_t launch_readout(int dim, int precision, const ReadArgs& a,
                           int blocks, hipStream_t s);
@@ -145,5 +153,7 @@ struct lbm_solver {
     hipStream_t own_stream;
     int device;
     bool split;
+    bool fd_fused;        // finite differences: one fused kernel (LANE / SPLIT variants)
+    void* fd_record;      // finite differences, two passes: per-cell record
     size_t device_bytes;
 };

@@ -24,7 +24,8 @@ pytestmark = pytest.mark.gpu
 
 R = lbm.lbm_lattice(37)[2]
 P64, P32 = lbm.LBM_FP64, lbm.LBM_FP32_DEV
-LANE, SPLIT = lbm.LBM_VARIANT_LANE, lbm.LBM_VARIANT_SPLIT
+AUTO, LANE, SPLIT = lbm.LBM_VARIANT_AUTO, lbm.LBM_VARIANT_LANE, lbm.LBM_VARIANT_SPLIT
+TWO = lbm.LBM_VARIANT_TWO_PASS
 
 CASE2D = dict(shape=(125, 111, 1), gamma=1.4, tf=0.1, tg=0.12, dt=0.25 / (3 * R))
 CASE3D = dict(shape=(48, 13, 11), gamma=1.4, tf=0.12, tg=0.12, dt=0.3 / (3 * R))
@@ -48,8 +49,11 @@ def fd3d():
     return f, oracle_run(3, *_args(c), f, 1000, dt=c["dt"])
 
 
+# TWO is the two-pass step (moments pass, then chunks of populations);
+# LANE and SPLIT the fused kernel in either layout
 @pytest.mark.parametrize("precision,variant,tol", [
-    (P64, LANE, TOL_FP64), (P64, SPLIT, TOL_FP64), (P32, LANE, TOL_FP32), (P32, SPLIT, TOL_FP32)])
+    (P64, TWO, TOL_FP64), (P32, TWO, TOL_FP32), (P64, LANE, TOL_FP64), (P64, SPLIT, TOL_FP64),
+    (P32, LANE, TOL_FP32), (P32, SPLIT, TOL_FP32)])
 def test_fd_2d_smooth_1000_steps(fd2d, precision, variant, tol):
     c = CASE2D
     f, o = fd2d
@@ -60,7 +64,7 @@ def test_fd_2d_smooth_1000_steps(fd2d, precision, variant, tol):
 
 
 @pytest.mark.parametrize("precision,variant,tol", [
-    (P64, SPLIT, TOL_FP64), (P32, SPLIT, TOL_FP32)])
+    (P64, TWO, TOL_FP64), (P32, TWO, TOL_FP32), (P64, SPLIT, TOL_FP64), (P32, SPLIT, TOL_FP32)])
 def test_fd_3d_smooth_1000_steps(fd3d, precision, variant, tol):
     c = CASE3D
     f, o = fd3d
@@ -77,12 +81,15 @@ def test_fd_3d_smooth_1000_steps(fd3d, precision, variant, tol):
     (3, (40, 17, 19), lbm.LBM_BC(0, 1, 0))])
 @pytest.mark.parametrize("precision,tol", [(P64, TOL_FP64), (P32, TOL_FP32)])
 def test_fd_tiny_open_and_banded_grids(dim, shape, bc, precision, tol):
-    # (70, 20) and (40, 17, 19): several waves per row, ragged last segment
+    # (70, 20) and (40, 17, 19): several waves per row, ragged last segment;
+    # both the two-pass step and the fused kernel
     dt = 0.25 / (3 * R)
     f = smooth_fields(dim, *shape, seed=13, a_rho=0.05, a_u=0.05, a_T=0.05)
     o = oracle_run(dim, 1.4, 0.1, 0.12, shape, f, 30, open_end=open_of(bc), dt=dt)
-    g = gpu_run(dim, 1.4, 0.1, 0.12, shape, f, 30, bc=bc, precision=precision, dt=dt)
-    assert_close(g, o, tol, f"FD {shape} bc={bc}")
+    for variant in (TWO, LANE if dim == 2 else SPLIT):
+        g = gpu_run(dim, 1.4, 0.1, 0.12, shape, f, 30, bc=bc, precision=precision, dt=dt,
+                    variant=variant)
+        assert_close(g, o, tol, f"FD {shape} bc={bc} variant={variant}")
 
 
 @pytest.mark.parametrize("precision", [P64, P32])
@@ -140,6 +147,10 @@ def test_fd_step_zero_and_determinism():
         assert np.array_equal(x, y)
     with lbm.Solver(2, 1.4, 0.1, 0.1, *shape, dt=dt) as s:
         assert s.info["scheme"] == 1 and s.info["dt"] == dt
+    with lbm.Solver(2, 1.4, 0.7, 0.7, *shape) as s:  # two passes: finite differences only
+        with pytest.raises(lbm.LBMError) as ei:
+            s.set_variant(TWO)
+        assert ei.value.code == lbm.LBM_EINVAL
 
 
 @pytest.mark.parametrize("dim", [3, 2])
