@@ -76,7 +76,8 @@ def describe(name, p):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "step_core.h", "velocity_set.h", "lbm_internal.h", "api.hip"):
+    for f in ("kernels.hip", "fd.hip", "step_core.h", "velocity_set.h", "lbm_internal.h",
+              "api.hip"):
         with open(os.path.join(ROOT, "paper_1608_06345_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
