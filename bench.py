@@ -143,7 +143,8 @@ def run_path(name, p, steps, warmup):
     }
 
 
-def serving_runs(measured_gbs, n_requests):
+def serving_runs(measured_gbs, n_requests, servers=("pool", "sequential"), ensemble=True,
+                 rate=None):
     """The batched serving form.
 
     tube_ensemble: 512 quasi-1D shock tubes (D2Q37, Nx log-uniform in
@@ -162,30 +163,38 @@ def serving_runs(measured_gbs, n_requests):
     from paper_1608_06345_amd import lbm, serving
 
     out = {}
-    tubes = serving.tube_ensemble(512, steps=1000, seed=4)
-    budget = sum(lbm.lbm_pool_request_bytes(r.req, lbm.LBM_FP32_DEV) for r in tubes) + (1 << 30)
-    tr, span = serving.serve_pool(tubes, budget, max_slots=600, ticks=1000, realtime=False)
-    out["tube_ensemble"] = dict(serving.summarize(tr, span), graph_steps=1000,
-                                workload="512 shock tubes, D2Q37 FP32, 1000 steps, one graph")
-    torch.cuda.empty_cache()
-    print(f"# tube ensemble: {out['tube_ensemble']}", file=sys.stderr, flush=True)
+    if ensemble:
+        tubes = serving.tube_ensemble(512, steps=1000, seed=4)
+        budget = (sum(lbm.lbm_pool_request_bytes(r.req, lbm.LBM_FP32_DEV) for r in tubes)
+                  + (1 << 30))
+        tr, span = serving.serve_pool(tubes, budget, max_slots=600, ticks=1000, realtime=False)
+        out["tube_ensemble"] = dict(serving.summarize(tr, span), graph_steps=1000,
+                                    workload="512 shock tubes, D2Q37 FP32, 1000 steps, one graph")
+        torch.cuda.empty_cache()
+        print(f"# tube ensemble: {out['tube_ensemble']}", file=sys.stderr, flush=True)
 
-    probe = serving.poisson_trace(400, 1.0, seed=5)
-    mean_bytes = np.mean([serving.request_bytes_moved(r) for r in probe if serving.valid(r)])
-    rate = 0.8 * measured_gbs * 1e9 / mean_bytes
-    trace = serving.poisson_trace(n_requests, rate, seed=5)
-    tr, span = serving.serve_pool(trace, 250 << 30, max_slots=256, ticks=8)
-    batched = serving.summarize(tr, span)
-    torch.cuda.empty_cache()
-    print(f"# serving, FP32 pool: {batched}", file=sys.stderr, flush=True)
-    trace = serving.poisson_trace(n_requests, rate, seed=5)
-    tr, span = serving.serve_sequential(trace, precision=lbm.LBM_FP64)
-    seq = serving.summarize(tr, span)
-    torch.cuda.empty_cache()
-    print(f"# serving, FP64 one at a time: {seq}", file=sys.stderr, flush=True)
-    out["poisson_trace"] = {"rate_per_s": round(rate, 3), "requests": n_requests,
-                            "fp32_pool_continuous_batching": batched,
-                            "fp64_single_solve_sequential": seq}
+    if rate is None:
+        probe = serving.poisson_trace(400, 1.0, seed=5)
+        mean_bytes = np.mean([serving.request_bytes_moved(r) for r in probe if serving.valid(r)])
+        rate = 0.8 * measured_gbs * 1e9 / mean_bytes
+    every = 50 if n_requests >= 200 else 0
+    pt = {"rate_per_s": round(rate, 3), "requests": n_requests}
+    if "pool" in servers:
+        trace = serving.poisson_trace(n_requests, rate, seed=5)
+        tr, span = serving.serve_pool(trace, 250 << 30, max_slots=256, ticks=8,
+                                      progress_every=every)
+        pt["fp32_pool_continuous_batching"] = serving.summarize(tr, span)
+        torch.cuda.empty_cache()
+        print(f"# serving, FP32 pool: {pt['fp32_pool_continuous_batching']}", file=sys.stderr,
+              flush=True)
+    if "sequential" in servers:
+        trace = serving.poisson_trace(n_requests, rate, seed=5)
+        tr, span = serving.serve_sequential(trace, precision=lbm.LBM_FP64, progress_every=every)
+        pt["fp64_single_solve_sequential"] = serving.summarize(tr, span)
+        torch.cuda.empty_cache()
+        print(f"# serving, FP64 one at a time: {pt['fp64_single_solve_sequential']}",
+              file=sys.stderr, flush=True)
+    out["poisson_trace"] = pt
     return out
 
 
@@ -253,6 +262,12 @@ def main():
                     help="skip the batched tube ensemble and the serving trace")
     ap.add_argument("--serving-requests", type=int, default=24,
                     help="requests in the Poisson serving trace")
+    ap.add_argument("--serving-only", choices=("pool", "sequential", "both"), default=None,
+                    help="after the headline path, run only the Poisson serving trace with "
+                         "these servers (no other paths, no tube ensemble, no CPU baseline)")
+    ap.add_argument("--serving-rate", type=float, default=None,
+                    help="arrival rate of the serving trace in requests/s (default: 80%% of "
+                         "the capacity estimated from the headline bandwidth)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy a device buffer of BYTES bytes 5 times (a plain copy "
                          "kernel of known size, to scale the HBM byte counters) and exit")
@@ -278,6 +293,8 @@ def main():
     res = run_path(args.path, head, args.steps, args.warmup)
     print(f"# {args.path}: {res['mlups']} MLUPS, {res['gbs']} GB/s", file=sys.stderr, flush=True)
     paths = {args.path: res}
+    if args.serving_only:
+        args.no_extra = args.no_cpu = True
     if not args.no_extra:
         for name, p in PATHS.items():
             if name == args.path:
@@ -311,8 +328,12 @@ def main():
                                             "ms_per_step", "steps")}
                   for k, v in paths.items()},
     }
-    if not args.no_serving:
-        out["serving"] = serving_runs(res["gbs"], args.serving_requests)
+    if args.serving_only:
+        servers = ("pool", "sequential") if args.serving_only == "both" else (args.serving_only,)
+        out["serving"] = serving_runs(res["gbs"], args.serving_requests, servers=servers,
+                                      ensemble=False, rate=args.serving_rate)
+    elif not args.no_serving:
+        out["serving"] = serving_runs(res["gbs"], args.serving_requests, rate=args.serving_rate)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(head)
     print(json.dumps(out), flush=True)

@@ -140,13 +140,21 @@ def _finish(r, rho, t0):
         r.note = "non-finite"
 
 
+def _progress(every, n_done, total, t0, what):
+    if every and n_done % every == 0:
+        import sys
+        print(f"# {what}: {n_done}/{total} requests done at "
+              f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+
 def serve_pool(trace, budget_bytes, max_slots=256, ticks=8, precision=lbm.LBM_FP32_DEV,
-               realtime=True, keep=None):
+               realtime=True, keep=None, progress_every=0):
     """Continuous batching of `trace` through one pool.  Returns the trace
     (with admitted / done / ok filled in) and the makespan in seconds.  With
     realtime=False every request is taken as arrived at t = 0.  `keep`, if
     given, is called as keep(request, pool, slot) before a finished slot is
-    released."""
+    released.  progress_every > 0 prints a line to stderr every that many
+    completions."""
     import torch
     pending = sorted([r for r in trace if valid(r)], key=lambda r: r.arrival)
     for r in trace:
@@ -155,6 +163,7 @@ def serve_pool(trace, budget_bytes, max_slots=256, ticks=8, precision=lbm.LBM_FP
     waiting = []
     resident = {}
     i = 0
+    n_done = 0
     stream = torch.cuda.Stream()
     with lbm.Pool(budget_bytes, max_slots, precision) as pool:
         pool.set_stream(stream)
@@ -196,18 +205,21 @@ def serve_pool(trace, budget_bytes, max_slots=256, ticks=8, precision=lbm.LBM_FP
                     keep(r, pool, slot)
                 _finish(r, rho, t0)
                 pool.release(slot)
+                n_done += 1
+                _progress(progress_every, n_done, len(pending), t0, "FP32 pool")
         makespan = time.perf_counter() - t0
     return trace, makespan
 
 
-def serve_sequential(trace, precision=lbm.LBM_FP64, realtime=True):
+def serve_sequential(trace, precision=lbm.LBM_FP64, realtime=True, progress_every=0):
     """The same trace, one request at a time, single-solve API, eager
     launches (no graphs), in arrival order."""
     import torch
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for r in sorted(trace, key=lambda r: r.arrival):
+    for n, r in enumerate(sorted(trace, key=lambda r: r.arrival)):
+        _progress(progress_every, n, len(trace), t0, "one at a time")
         if not valid(r):
             r.ok, r.note = False, "rejected: gamma gives delta < 0"
             continue
