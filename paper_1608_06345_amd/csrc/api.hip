@@ -342,6 +342,7 @@ int lbm_init_fields_dev(lbm_handle h, const double* rho, const double* u, const 
     LBM_HIP(lbm::launch_init(h->dim, h->precision, h->buf[0], rho, u, T, h->N, 0.5 * h->delta,
                              h->lat->r, h->lat->w_group, h->stream));
     if (h->scheme) {  // finite differences keep S_n itself
+        h->fd_record_valid = false;
         h->cur = 0;
         h->initial = true;
         h->have_state = true;
@@ -379,11 +380,14 @@ int lbm_step(lbm_handle h, int64_t n) {
     if (!h->have_state) return LBM_ESTATE;
     for (int64_t k = 0; k < n; ++k) {
         const lbm::StepArgs a = step_args(h, h->buf[h->cur], h->buf[h->cur ^ 1], true);
-        if (h->scheme && h->fd_fused)
+        if (h->scheme && h->fd_fused) {
             LBM_HIP(lbm::launch_fd_step(h->dim, h->precision, h->split, a, h->stream));
-        else if (h->scheme)
-            LBM_HIP(lbm::launch_fd_two_pass(h->dim, h->precision, a, h->fd_record, h->stream));
-        else
+            h->fd_record_valid = false;
+        } else if (h->scheme) {
+            LBM_HIP(lbm::launch_fd_two_pass(h->dim, h->precision, a, h->fd_record,
+                                            h->fd_record_valid, h->stream));
+            h->fd_record_valid = true;
+        } else
             LBM_HIP(lbm::launch_step(h->dim, h->precision, h->split, a, h->stream));
         h->cur ^= 1;
         h->initial = false;

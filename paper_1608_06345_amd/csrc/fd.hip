@@ -13,7 +13,11 @@
 //   update passes one lane per cell, a chunk of populations per launch:
 //                 the chunk's targets from the record, relaxation with
 //                 rates dt / tau and the upwind convection, whose neighbour
-//                 rows -- a chunk's planes only -- stay in the L2.
+//                 rows -- a chunk's planes only -- stay in the L2.  Each
+//                 pass also adds its new populations' moment sums into a
+//                 per-cell accumulator, and the last one turns the totals
+//                 into the next step's record, so in FP32 the moments pass
+//                 runs only after the state was set from outside (init).
 //
 // The arithmetic is that of the fused kernel: the same equilibrium, the
 // same target sums for the correction (accumulated in the same order), the
@@ -33,6 +37,15 @@ using namespace core;
 //   deviation storage only: D+3 dm_g, D+4 .. 2D+3 dj_g, 2D+4 de_g, 2D+5 dm_h.
 template <int D, bool DEV>
 constexpr int kRecFields = DEV ? 2 * D + 6 : D + 3;
+// After the record: the running moment sums of the new state, s0, sj (D),
+// se and sh (sum of h), accumulated chunk by chunk.  Only in FP32 deviation
+// storage: in FP64 the accumulator's read-modify-write per chunk (96 B per
+// cell) costs more than the moments pass it saves (D3Q107 256^3: 32.0 ms
+// against 30.4 ms per step), so FP64 runs the moments pass every step.
+template <int D>
+constexpr int kAccFields = D + 3;
+template <class P>
+constexpr bool kAccumulate = !std::is_same_v<P, F64>;
 
 // Population chunks of the update passes: the rest and axis populations
 // (which take the correction) with the first pairs, then 14 at a time.
@@ -98,32 +111,15 @@ __device__ __forceinline__ void target_residuals(const Equilibrium<D, T, true>& 
     if constexpr (D == 3) dj[2] = je_on * (want_j[2] - sjz);
 }
 
+// The record of one cell from its moment sums (g: s0, sj, se; h: sh).
 template <int D, class P>
-__global__ __launch_bounds__(256) void k_fd_moments(const void* __restrict__ src_v,
-                                                    typename P::T* __restrict__ rec, int64_t N,
-                                                    const Physics ph) {
+__device__ __forceinline__ void write_record(typename P::T s0, typename P::T sx,
+                                             typename P::T sy, typename P::T sz,
+                                             typename P::T se, typename P::T sh,
+                                             typename P::T* __restrict__ rec, int64_t N,
+                                             int64_t cell, const Physics& ph) {
     using T = typename P::T;
-    using S = typename P::S;
     constexpr bool DEV = P::kDev;
-    constexpr VelSet<D> V = kVelSet<D>;
-    constexpr int Q = VelSet<D>::Q;
-    const int64_t cell = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (cell >= N) return;  // lanes are independent here
-    const S* src = static_cast<const S*>(src_v);
-    // running sums over the centre values (moment_sums, streamed)
-    T s0 = 0, sx = 0, sy = 0, sz = 0, se = 0, sh = 0;
-    static_for<0, Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        constexpr Vel v = V.v[i];
-        const T x = from_store<P>(src[(size_t)(2 * i) * N + cell], ph, v.group);
-        const T y = from_store<P>(src[(size_t)(2 * i + 1) * N + cell], ph, v.group);
-        s0 += x;
-        if constexpr (v.x != 0) sx += T(v.x) * x;
-        if constexpr (v.y != 0) sy += T(v.y) * x;
-        if constexpr (D == 3 && v.z != 0) sz += T(v.z) * x;
-        if constexpr (V.qn[v.group] != 0) se += T(V.qn[v.group]) * x;
-        sh += y;
-    });
     T sj[3] = {sx, sy, sz};
     T rho, drho, u[3] = {0, 0, 0}, t;
     macro<D, T, DEV>(s0, sj, se, sh, T(ph.r), ph.inv_dof, ph.half_delta, rho, drho, u, t);
@@ -152,13 +148,42 @@ __global__ __launch_bounds__(256) void k_fd_moments(const void* __restrict__ src
     }
 }
 
+template <int D, class P>
+__global__ __launch_bounds__(256) void k_fd_moments(const void* __restrict__ src_v,
+                                                    typename P::T* __restrict__ rec, int64_t N,
+                                                    const Physics ph) {
+    using T = typename P::T;
+    using S = typename P::S;
+    constexpr bool DEV = P::kDev;
+    constexpr VelSet<D> V = kVelSet<D>;
+    constexpr int Q = VelSet<D>::Q;
+    const int64_t cell = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (cell >= N) return;  // lanes are independent here
+    const S* src = static_cast<const S*>(src_v);
+    // running sums over the centre values (moment_sums, streamed)
+    T s0 = 0, sx = 0, sy = 0, sz = 0, se = 0, sh = 0;
+    static_for<0, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr Vel v = V.v[i];
+        const T x = from_store<P>(src[(size_t)(2 * i) * N + cell], ph, v.group);
+        const T y = from_store<P>(src[(size_t)(2 * i + 1) * N + cell], ph, v.group);
+        s0 += x;
+        if constexpr (v.x != 0) sx += T(v.x) * x;
+        if constexpr (v.y != 0) sy += T(v.y) * x;
+        if constexpr (D == 3 && v.z != 0) sz += T(v.z) * x;
+        if constexpr (V.qn[v.group] != 0) se += T(V.qn[v.group]) * x;
+        sh += y;
+    });
+    write_record<D, P>(s0, sx, sy, sz, se, sh, rec, N, cell, ph);
+}
+
 // Update of populations [C0, C1) of every cell: target, relaxation with the
 // convection centre term, neighbour terms, store (see relax and
 // convect_store_* for the same steps in the fused kernel).
 template <int D, class P, int C0, int C1>
 __global__ __launch_bounds__(256) void k_fd_update(const void* __restrict__ src_v,
                                                    void* __restrict__ dst_v,
-                                                   const typename P::T* __restrict__ rec,
+                                                   typename P::T* __restrict__ rec,
                                                    const StepArgs a) {
     using T = typename P::T;
     using S = typename P::S;
@@ -231,6 +256,9 @@ __global__ __launch_bounds__(256) void k_fd_update(const void* __restrict__ src_
         if constexpr (D == 3) o += ax == 2 ? pt.z[3 - d] : pt.z[3];
         return o;
     };
+    // moment sums of the new populations of this chunk (next step's record)
+    constexpr bool ACC = kAccumulate<P>;
+    T a0 = 0, ax = 0, ay = 0, az = 0, ae = 0, ah = 0;
     static_for<C0, C1>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr Vel v = V.v[i];
@@ -294,15 +322,44 @@ __global__ __launch_bounds__(256) void k_fd_update(const void* __restrict__ src_
                                T(2) * from_store<P>(src[ph_off + oa], ph, g));
             }
         });
+        const T ng = xg - cs * nbg;
+        const T nh = xh - cs * nbh;
         store_at(reinterpret_cast<char*>(dst + pg_off), (uint32_t)(cell * sizeof(S)),
-                 to_store<P>(xg - cs * nbg, ph, g));
+                 to_store<P>(ng, ph, g));
         store_at(reinterpret_cast<char*>(dst + ph_off), (uint32_t)(cell * sizeof(S)),
-                 to_store<P>(xh - cs * nbh, ph, g));
+                 to_store<P>(nh, ph, g));
+        if constexpr (ACC) {
+            a0 += ng;
+            if constexpr (v.x != 0) ax += T(v.x) * ng;
+            if constexpr (v.y != 0) ay += T(v.y) * ng;
+            if constexpr (D == 3 && v.z != 0) az += T(v.z) * ng;
+            if constexpr (V.qn[g] != 0) ae += T(V.qn[g]) * ng;
+            ah += nh;
+        }
     });
+    if constexpr (!ACC) return;
+    // running sums: the first chunk starts them, the last turns the totals
+    // into the next step's record (this lane has read its cell's record)
+    T* acc = rec + (size_t)kRecFields<D, DEV> * N;
+    T sums[6] = {a0, ax, ay, az, ae, ah};
+    constexpr int kSlots[6] = {0, 1, 2, D == 3 ? 3 : -1, D + 1, D + 2};
+    if constexpr (C0 != 0) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            if (kSlots[k] >= 0) sums[k] += acc[(size_t)kSlots[k] * N + cell];
+    }
+    if constexpr (C1 == VelSet<D>::Q) {
+        write_record<D, P>(sums[0], sums[1], sums[2], sums[3], sums[4], sums[5], rec, N, cell,
+                           ph);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            if (kSlots[k] >= 0) acc[(size_t)kSlots[k] * N + cell] = sums[k];
+    }
 }
 
 template <int D, class P, int C>
-hipError_t launch_chunks(const StepArgs& a, const typename P::T* rec, int grid, hipStream_t s) {
+hipError_t launch_chunks(const StepArgs& a, typename P::T* rec, int grid, hipStream_t s) {
     if constexpr (C == chunk_count<D>()) {
         return hipSuccess;
     } else {
@@ -319,14 +376,16 @@ hipError_t launch_chunks(const StepArgs& a, const typename P::T* rec, int grid, 
 constexpr int64_t kFdWindowBytes = 2 << 20;
 
 template <int D, class P>
-hipError_t fd_two_pass_impl(const StepArgs& a0, void* rec_v, hipStream_t s) {
+hipError_t fd_two_pass_impl(const StepArgs& a0, void* rec_v, bool record_valid, hipStream_t s) {
     using T = typename P::T;
     StepArgs a = a0;
     T* rec = static_cast<T*>(rec_v);
     const int tiles = (int)((a.N + 255) / 256);
-    hipError_t e = launch_kernel(&k_fd_moments<D, P>, dim3(tiles), dim3(256), s, a.src, rec, a.N,
-                                 a.ph);
-    if (e != hipSuccess) return e;
+    if (!record_valid || !kAccumulate<P>) {
+        hipError_t e = launch_kernel(&k_fd_moments<D, P>, dim3(tiles), dim3(256), s, a.src, rec,
+                                     a.N, a.ph);
+        if (e != hipSuccess) return e;
+    }
     // one x-row tile of one chunk's planes (at most 14 populations, g and h)
     const int64_t tile_bytes = 256LL * 2 * kChunkW * (int64_t)sizeof(typename P::S);
     a.tiles_per_row = (a.nx + 255) / 256;
@@ -358,20 +417,20 @@ hipError_t fd_two_pass_impl(const StepArgs& a0, void* rec_v, hipStream_t s) {
 }  // namespace
 
 size_t fd_record_bytes(int dim, int precision, int64_t N) {
-    const bool dev = precision != LBM_FP64;
-    const int fields = dim == 2 ? (dev ? kRecFields<2, true> : kRecFields<2, false>)
-                                : (dev ? kRecFields<3, true> : kRecFields<3, false>);
+    const bool dev = precision != LBM_FP64;  // deviation storage: record + accumulator
+    const int fields = dim == 2 ? (dev ? kRecFields<2, true> + kAccFields<2> : kRecFields<2, false>)
+                                : (dev ? kRecFields<3, true> + kAccFields<3> : kRecFields<3, false>);
     return (size_t)fields * (size_t)N * (precision == LBM_FP64 ? 8 : 4);
 }
 
 hipError_t launch_fd_two_pass(int dim, int precision, const StepArgs& a, void* record,
-                              hipStream_t s) {
+                              bool record_valid, hipStream_t s) {
     if (precision == LBM_FP64)
-        return dim == 2 ? fd_two_pass_impl<2, F64>(a, record, s)
-                        : fd_two_pass_impl<3, F64>(a, record, s);
+        return dim == 2 ? fd_two_pass_impl<2, F64>(a, record, record_valid, s)
+                        : fd_two_pass_impl<3, F64>(a, record, record_valid, s);
     if (precision == LBM_FP32_DEV)
-        return dim == 2 ? fd_two_pass_impl<2, F32Dev>(a, record, s)
-                        : fd_two_pass_impl<3, F32Dev>(a, record, s);
+        return dim == 2 ? fd_two_pass_impl<2, F32Dev>(a, record, record_valid, s)
+                        : fd_two_pass_impl<3, F32Dev>(a, record, record_valid, s);
     return hipErrorInvalidValue;
 }
 

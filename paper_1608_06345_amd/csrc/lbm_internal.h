@@ -115,11 +115,12 @@ hipError_t launch_step(int dim, int precision, bool split, const StepArgs& a,
 hipError_t launch_fd_step(int dim, int precision, bool split, const StepArgs& a,
                           hipStream_t s);
 // The same step in two passes (fd.hip): a moments pass writing a per-cell
-// record, then update passes over chunks of populations.  FP64 and FP32
-// deviation storage.
+// record, then update passes over chunks of populations, which also leave
+// the next step's record behind (record_valid: skip the moments pass).
+// FP64 and FP32 deviation storage.
 size_t fd_record_bytes(int dim, int precision, int64_t N);
 hipError_t launch_fd_two_pass(int dim, int precision, const StepArgs& a, void* record,
-                              hipStream_t s);
+                              bool record_valid, hipStream_t s);
 int step_block_cells(int dim, int precision, bool split);
 hipError_t launch_readout(int dim, int precision, const ReadArgs& a,
                           int blocks, hipStream_t s);
@@ -155,5 +156,6 @@ struct lbm_solver {
     bool split;
     bool fd_fused;        // finite differences: one fused kernel (LANE / SPLIT variants)
     void* fd_record;      // finite differences, two passes: per-cell record
+    bool fd_record_valid; // the record describes the current state
     size_t device_bytes;
 };
