@@ -3,7 +3,9 @@
  * scheme with arbitrary specific-heat ratio of Hu, Zhang & Geng
  * (arXiv:1608.06345): two reduced distributions per cell, g (mass and
  * momentum) and h (internal energy), on the D2Q37 and D3Q107 velocity sets,
- * advanced by a fused BGK collide-and-stream step.
+ * advanced by a fused BGK collide-and-stream step (lbm_create, lbm_create_ex)
+ * or by the paper's finite-difference form (lbm_create_fd), one solve per
+ * handle or many per pool (lbm_pool_*).
  *
  * The method, section by section:
  *   Sec. II   the reduced distributions g and h; the moments
@@ -31,8 +33,9 @@
  *     by lbm_destroy.
  *   - A handle is not thread-safe; separate handles are independent.
  *   - State convention: S_0 is the equilibrium of the initial fields and one
- *     step is S_{n+1} = Stream(Collide(S_n)).  lbm_moments and lbm_totals
- *     report S_n, the pre-collision state after n steps.
+ *     step is S_{n+1} = Stream(Collide(S_n)) (lattice streaming) or one
+ *     explicit finite-difference step (lbm_create_fd).  lbm_moments and
+ *     lbm_totals report S_n, the pre-collision state after n steps.
  */
 #ifndef LBM_H
 #define LBM_H
@@ -157,23 +160,24 @@ int lbm_destroy(lbm_handle h);
  * null stream).  Until this is called a handle uses a non-blocking stream of
  * its own.  The stream is borrowed, not owned: it must outlive its use. */
 int lbm_set_stream(lbm_handle h, void *stream);
-/* Kernel layout of the fused step (a tuning choice; results agree to
- * round-off).  LANE: one lane holds all 2Q populations of a cell.  SPLIT: a
- * lane pair holds them, g in lane l and h in lane l + 32 of the wave.  AUTO
- * (the default) takes LANE for D2Q37 and SPLIT for D3Q107, whose 214
- * populations do not fit one lane's registers.  EINVAL for other values. */
+/* Kernel layout of the step (a tuning choice; results agree to round-off).
+ *   LANE      fused kernel, one lane holds all 2Q populations of a cell;
+ *   SPLIT     fused kernel, a lane pair holds them, g in lane l and h in
+ *             lane l + 32 of the wave;
+ *   TWO_PASS  (lbm_create_fd solves only) the finite-difference step as a
+ *             moments pass plus updates of chunks of populations, which
+ *             keeps each chunk's neighbour rows in cache;
+ *   AUTO      (the default) lattice streaming: LANE for D2Q37, SPLIT for
+ *             D3Q107, whose 214 populations do not fit one lane's
+ *             registers; finite differences: TWO_PASS, except LANE for
+ *             D2Q37 in FP64, where the fused kernel is faster.
+ * EINVAL for other values, and for TWO_PASS on a lattice-streaming solve. */
 enum lbm_variant {
     LBM_VARIANT_AUTO = 0,
     LBM_VARIANT_LANE = 1,
     LBM_VARIANT_SPLIT = 2,
     LBM_VARIANT_TWO_PASS = 3
 };
-/* For solves made with lbm_create_fd: TWO_PASS runs the finite-difference
- * step in two passes -- a moments pass, then updates of chunks of
- * populations, which keeps each chunk's neighbour rows in cache; LANE and
- * SPLIT run it as one fused kernel in the named layout; AUTO takes TWO_PASS
- * except for D2Q37 in FP64, where the fused kernel is faster.  TWO_PASS is
- * EINVAL for lattice-streaming solves. */
 int lbm_set_variant(lbm_handle h, int variant);
 
 /* Block until the handle's stream is idle. */
@@ -189,9 +193,10 @@ int lbm_init_fields(lbm_handle h, const double *rho, const double *u,
 int lbm_init_fields_dev(lbm_handle h, const double *rho, const double *u,
                         const double *T);
 
-/* Advance n >= 0 steps (collide, then stream every population e_i cells),
- * asynchronously on the handle's stream.  ESTATE before init; EINVAL for
- * n < 0. */
+/* Advance n >= 0 steps, asynchronously on the handle's stream: collide, then
+ * stream every population e_i cells (lattice streaming), or n explicit
+ * finite-difference steps of size dt (lbm_create_fd).  ESTATE before init;
+ * EINVAL for n < 0. */
 int lbm_step(lbm_handle h, int64_t n);
 
 /* Moments of S_n (Sec. II): rho [ncells], u [dim][ncells] and the specific
@@ -222,8 +227,10 @@ typedef struct {
 } lbm_info;
 int lbm_get_info(lbm_handle h, lbm_info *info);
 
-/* Device bytes a solve of this shape holds (two distributions, two
- * ping-pong copies, plus reduction scratch); 0 for invalid arguments. */
+/* Device bytes a lattice-streaming solve of this shape holds (two
+ * distributions, two ping-pong copies, plus reduction scratch); 0 for
+ * invalid arguments.  A finite-difference solve holds a per-cell record on
+ * top (lbm_info.device_bytes has the total). */
 size_t lbm_footprint_bytes(int dim, int velocity_set, int precision,
                            int64_t nx, int64_t ny, int64_t nz);
 
@@ -242,8 +249,10 @@ int lbm_lattice(int velocity_set, int8_t *e, double *w, double *r);
  * counter launch), and lbm_pool_run replays K such steps from a captured
  * hipGraph.  Membership lives in device tables, so solves can be admitted and
  * released between replays without re-capturing (continuous batching).  Each
- * solve follows exactly the single-solve scheme and state convention above;
- * its arithmetic does not depend on which other solves are resident.
+ * solve follows exactly the single-solve scheme and state convention above
+ * (lattice streaming, the paper's collision: the finite-difference form and
+ * the energy-conserving collision are single-solve options); its arithmetic
+ * does not depend on which other solves are resident.
  * All pool memory is owned by the pool.  A pool is not thread-safe.
  * ---------------------------------------------------------------------- */
 typedef struct lbm_pool *lbm_pool_handle;

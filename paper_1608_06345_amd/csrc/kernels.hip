@@ -1,5 +1,6 @@
 // HIP kernels for gfx950: initialisation, the fused collide-and-stream step,
-// and the FP64 readout / conservation reductions.
+// the fused finite-difference step (Sec. III; its two-pass form is in
+// fd.hip), and the FP64 readout / conservation reductions.
 //
 // Data layout in HBM (one ping-pong side): [Q][2][N] -- for population i the
 // g plane (N values, x fastest) and then the h plane.  Every plane is read

@@ -1,7 +1,8 @@
-// Device code shared by the single-solve kernels (kernels.hip) and the
-// batched multi-solve kernels (pool.hip): memory helpers, the pull offsets,
-// the moments, the 4th-order equilibrium, the BGK relaxation, and the whole
-// per-cell collision in the two register layouts.
+// Device code shared by the single-solve kernels (kernels.hip, fd.hip) and
+// the batched multi-solve kernels (pool.hip): memory helpers, the pull
+// offsets, the moments, the 4th-order equilibrium, the BGK relaxation (with
+// the finite-difference and energy-conserving variants), the storage
+// precisions, and the whole per-cell collision in the two register layouts.
 #pragma once
 
 #include <type_traits>
