@@ -13,11 +13,15 @@
 //   update passes one lane per cell, a chunk of populations per launch:
 //                 the chunk's targets from the record, relaxation with
 //                 rates dt / tau and the upwind convection, whose neighbour
-//                 rows -- a chunk's planes only -- stay in the L2.  Each
-//                 pass also adds its new populations' moment sums into a
-//                 per-cell accumulator, and the last one turns the totals
-//                 into the next step's record, so in FP32 the moments pass
-//                 runs only after the state was set from outside (init).
+//                 rows -- a chunk's planes only -- stay in the L2.  Where
+//                 rows are whole 256-cell tiles, a workgroup stages each
+//                 population's stencil rows in LDS with 16-byte loads
+//                 (k_fd_update_lds); otherwise each lane reads its stencil
+//                 from global memory (k_fd_update).  Each pass also adds its
+//                 new populations' moment sums into a per-cell accumulator,
+//                 and the last one turns the totals into the next step's
+//                 record, so in FP32 the moments pass runs only after the
+//                 state was set from outside (init).
 //
 // The arithmetic is that of the fused kernel: the same equilibrium, the
 // same target sums for the correction (accumulated in the same order), the
@@ -48,21 +52,25 @@ template <class P>
 constexpr bool kAccumulate = !std::is_same_v<P, F64>;
 
 // Population chunks of the update passes: the rest and axis populations
-// (which take the correction) with the first pairs, then 14 at a time.
+// (which take the correction) with the first pairs, then 21 at a time in 3D
+// (6 launches) and the other 24 in 2D (2 launches).  Wider chunks read the
+// record and the accumulator fewer times; 28 in 3D was slower again
+// (measured at 256^3).
 template <int D>
 constexpr int kChunk0 = D == 2 ? 13 : 15;
-constexpr int kChunkW = 14;
+template <int D>
+constexpr int kChunkW = D == 2 ? 24 : 21;
 template <int D>
 constexpr int chunk_count() {
     constexpr int Q = VelSet<D>::Q;
-    return 1 + (Q - kChunk0<D> + kChunkW - 1) / kChunkW;
+    return 1 + (Q - kChunk0<D> + kChunkW<D> - 1) / kChunkW<D>;
 }
 template <int D>
-constexpr int chunk_begin(int c) { return c == 0 ? 0 : kChunk0<D> + (c - 1) * kChunkW; }
+constexpr int chunk_begin(int c) { return c == 0 ? 0 : kChunk0<D> + (c - 1) * kChunkW<D>; }
 template <int D>
 constexpr int chunk_end(int c) {
     constexpr int Q = VelSet<D>::Q;
-    const int e = kChunk0<D> + c * kChunkW;
+    const int e = kChunk0<D> + c * kChunkW<D>;
     return c == 0 ? kChunk0<D> : (e < Q ? e : Q);
 }
 
@@ -177,27 +185,15 @@ __global__ __launch_bounds__(256) void k_fd_moments(const void* __restrict__ src
     write_record<D, P>(s0, sx, sy, sz, se, sh, rec, N, cell, ph);
 }
 
-// Update of populations [C0, C1) of every cell: target, relaxation with the
-// convection centre term, neighbour terms, store (see relax and
-// convect_store_* for the same steps in the fused kernel).
-template <int D, class P, int C0, int C1>
-__global__ __launch_bounds__(256) void k_fd_update(const void* __restrict__ src_v,
-                                                   void* __restrict__ dst_v,
-                                                   typename P::T* __restrict__ rec,
-                                                   const StepArgs a) {
-    using T = typename P::T;
-    using S = typename P::S;
-    constexpr bool DEV = P::kDev;
-    constexpr VelSet<D> V = kVelSet<D>;
-    const int64_t N = a.N;
-    // Sweep order (2.5D blocking).  A tile is 256 cells of one x-row.  The
-    // rows are cut into y sub-bands of fd_yb rows, dealt to the XCDs round-
-    // robin (sub-band s to XCD s % 8, which is workgroup b % 8); an XCD sweeps
-    // each of its sub-bands x-chunk (fd_w tiles) by x-chunk, and within a
-    // chunk z-slab by z-slab, row by row.  The planes a stencil reads at
-    // y +- 1, 2 and z +- 1, 2 were then fetched by the same XCD within the
-    // last few sub-band slabs, which the host sizes to stay in its L2.
-    const int b = (int)blockIdx.x;
+// Sweep order of the update passes (2.5D blocking).  A tile is 256 cells of
+// one x-row.  The rows are cut into y sub-bands of fd_yb rows, dealt to the
+// XCDs round-robin (sub-band s to XCD s % 8, which is workgroup b % 8); an
+// XCD sweeps each of its sub-bands x-chunk (fd_w tiles) by x-chunk, and
+// within a chunk z-slab by z-slab, row by row.  The planes a stencil reads
+// at y +- 1, 2 and z +- 1, 2 were then fetched by the same XCD within the
+// last few sub-band slabs, which the host sizes to stay in its L2.  Returns
+// false for the padding workgroups of the last round.
+__device__ __forceinline__ bool sweep_tile(const StepArgs& a, int b, int& xt, int& cy, int& cz) {
     const int W = a.fd_w, YB = a.fd_yb;
     const int chunks = (a.tiles_per_row + W - 1) / W;
     const int per_chunk = W * YB * a.nz;
@@ -207,63 +203,71 @@ __global__ __launch_bounds__(256) void k_fd_update(const void* __restrict__ src_
     const int in_sub = j - round * per_sub;
     const int chunk = in_sub / per_chunk;
     const int in_chunk = in_sub - chunk * per_chunk;
-    const int cz = in_chunk / (YB * W);
+    cz = in_chunk / (YB * W);
     const int in_slab = in_chunk - cz * (YB * W);
-    const int cy = (round * 8 + (b & 7)) * YB + in_slab / W;
-    const int xt = chunk * W + in_slab % W;
-    const int cx = xt * 256 + (int)threadIdx.x;
-    if (xt >= a.tiles_per_row || cy >= a.ny || cx >= a.nx) return;
-    const int64_t cell = (int64_t)cx + (int64_t)a.nx * cy + (int64_t)a.nxy * cz;
-    const Physics& ph = a.ph;
-    PullTable<D> pt;  // pt.src for shift e gives the cell at x - e (wrapped or clamped)
-    pt.fill(cx, cy, cz, a.nx, a.ny, a.nz, a.nxy, a.open_end, true);
-    const S* src = static_cast<const S*>(src_v);
-    S* dst = static_cast<S*>(dst_v);
+    cy = (round * 8 + (b & 7)) * YB + in_slab / W;
+    xt = chunk * W + in_slab % W;
+    return xt < a.tiles_per_row && cy < a.ny;
+}
 
-    const T m0 = rec[cell];
-    T u[3] = {0, 0, 0};
-#pragma unroll
-    for (int k = 0; k < D; ++k) u[k] = rec[(size_t)(1 + k) * N + cell];
-    const T t = rec[(size_t)(D + 1) * N + cell];
-    const T kr = rec[(size_t)(D + 2) * N + cell];
-    const T rho = DEV ? T(1) + m0 : m0;
-    const T drho = DEV ? m0 : m0 - T(1);
+// One cell of an update pass over populations [C0, C1): the record's
+// macroscopic state and equilibrium, the correction residuals (first chunk
+// only: it holds the rest and axis populations that take them), and the
+// running moment sums of the new populations.  Both update kernels run
+// these steps in this order; they differ only in where a stencil's stored
+// values come from.
+template <int D, class P, int C0, int C1>
+struct FdCell {
+    using T = typename P::T;
+    using S = typename P::S;
+    static constexpr bool DEV = P::kDev;
+    static constexpr bool ACC = kAccumulate<P>;
     Equilibrium<D, T, DEV> eq;
-    eq.setup(u, t, T(ph.r));
-    const T hd = T(ph.half_delta);
-    const T hdT = hd * (T(1) + t);
-    const T arho_h = hdT * rho + kr;
-    const T beta_g = DEV ? drho : T(0);
-    const T beta_h = DEV ? hdT * drho + hd * t + kr : T(0);
-    // correction residuals: only the first chunk holds the rest and axis
-    // populations that take them
+    T rho, arho_h, beta_g, beta_h, omf, omg, cs;
     T dm = 0, de = 0, dmh = 0, dj[3] = {0, 0, 0};
-    if constexpr (DEV && C0 == 0) {
-        dm = rec[(size_t)(D + 3) * N + cell];
-#pragma unroll
-        for (int k = 0; k < D; ++k) dj[k] = rec[(size_t)(D + 4 + k) * N + cell];
-        de = rec[(size_t)(2 * D + 4) * N + cell];
-        dmh = rec[(size_t)(2 * D + 5) * N + cell];
-    }
-    const T omf = T(ph.omega_f), omg = T(ph.omega_g);
-    const T cs = fd_scale<T>(ph);
-    // offset of the neighbour x + d along axis A of this cell
-    auto nbr = [&](auto Ax, auto Dd) {
-        constexpr int ax = decltype(Ax)::value;
-        constexpr int d = decltype(Dd)::value;
-        int o = ax == 0 ? pt.x[3 - d] : pt.x[3];
-        o += ax == 1 ? pt.y[3 - d] : pt.y[3];
-        if constexpr (D == 3) o += ax == 2 ? pt.z[3 - d] : pt.z[3];
-        return o;
-    };
-    // moment sums of the new populations of this chunk (next step's record)
-    constexpr bool ACC = kAccumulate<P>;
     T a0 = 0, ax = 0, ay = 0, az = 0, ae = 0, ah = 0;
-    static_for<C0, C1>([&](auto I) {
-        constexpr int i = decltype(I)::value;
+
+    __device__ __forceinline__ void load(const T* __restrict__ rec, int64_t N, int64_t cell,
+                                         const Physics& ph) {
+        const T m0 = rec[cell];
+        T u[3] = {0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < D; ++k) u[k] = rec[(size_t)(1 + k) * N + cell];
+        const T t = rec[(size_t)(D + 1) * N + cell];
+        // kappa rho is zero unless the energy-conserving collision is on
+        const T kr = ph.ec != 0 ? rec[(size_t)(D + 2) * N + cell] : T(0);
+        rho = DEV ? T(1) + m0 : m0;
+        const T drho = DEV ? m0 : m0 - T(1);
+        eq.setup(u, t, T(ph.r));
+        const T hd = T(ph.half_delta);
+        const T hdT = hd * (T(1) + t);
+        arho_h = hdT * rho + kr;
+        beta_g = DEV ? drho : T(0);
+        beta_h = DEV ? hdT * drho + hd * t + kr : T(0);
+        if constexpr (DEV && C0 == 0) {
+            dm = rec[(size_t)(D + 3) * N + cell];
+#pragma unroll
+            for (int k = 0; k < D; ++k) dj[k] = rec[(size_t)(D + 4 + k) * N + cell];
+            de = rec[(size_t)(2 * D + 4) * N + cell];
+            dmh = rec[(size_t)(2 * D + 5) * N + cell];
+        }
+        omf = T(ph.omega_f);
+        omg = T(ph.omega_g);
+        cs = fd_scale<T>(ph);
+    }
+
+    // Population i: target (uncorrected w (arho P~(c) + beta), +- pair
+    // arithmetic, plus the correction on the rest and axis populations),
+    // relaxation with the convection centre term (relax<..., FD>), neighbour
+    // terms (fd_neighbours), store.  at(dist, axis, d) is the stored value
+    // of distribution dist (0: g, 1: h) at the neighbour x + d along axis
+    // (d = 0: the cell itself).
+    template <int i, class At>
+    __device__ __forceinline__ void update(const Physics& ph, At&& at, S* __restrict__ dst,
+                                           int64_t N, int64_t cell) {
+        constexpr VelSet<D> V = kVelSet<D>;
         constexpr Vel v = V.v[i];
         constexpr int g = v.group;
-        // target (uncorrected): w (arho P~(c) + beta), +- pair arithmetic
         T A0, A1, A2;
         eq.template coef<V.qn[g]>(A0, A1, A2);
         const T w = weight<T>(ph, g);
@@ -291,10 +295,11 @@ __global__ __launch_bounds__(256) void k_fd_update(const void* __restrict__ src_
             const T half = T(0.5) * dj[axis];
             tg += s > 0 ? de * T(1.0 / (2 * D)) + half : de * T(1.0 / (2 * D)) - half;
         }
-        // relaxation with the convection centre term (relax<…, FD>)
-        const size_t pg_off = (size_t)(2 * i) * N, ph_off = pg_off + N;
-        T xg = from_store<P>(src[pg_off + cell], ph, g);
-        T xh = from_store<P>(src[ph_off + cell], ph, g);
+        using Z = std::integral_constant<int, 0>;
+        using G = std::integral_constant<int, 0>;
+        using H = std::integral_constant<int, 1>;
+        T xg = from_store<P>(at(G{}, Z{}, Z{}), ph, g);
+        T xh = from_store<P>(at(H{}, Z{}, Z{}), ph, g);
         if constexpr (l1_of(v) != 0) {
             const T kc = T(3 * l1_of(v)) * cs;
             xg = (xg - kc * xg) + omf * (tg - xg);
@@ -303,27 +308,27 @@ __global__ __launch_bounds__(256) void k_fd_update(const void* __restrict__ src_
             xg = xg + omf * (tg - xg);
             xh = xh + omg * (th - xh);
         }
-        // neighbour terms (fd_neighbours)
         T nbg = T(0), nbh = T(0);
         static_for<0, D>([&](auto A) {
-            constexpr int ax = decltype(A)::value;
-            constexpr int e = ax == 0 ? v.x : (ax == 1 ? v.y : v.z);
+            constexpr int ax_ = decltype(A)::value;
+            constexpr int e = ax_ == 0 ? v.x : (ax_ == 1 ? v.y : v.z);
             if constexpr (e != 0) {
                 constexpr int s = e > 0 ? 1 : -1;
                 constexpr int m = e > 0 ? e : -e;
-                const int o2 = nbr(A, std::integral_constant<int, -2 * s>{});
-                const int o1 = nbr(A, std::integral_constant<int, -s>{});
-                const int oa = nbr(A, std::integral_constant<int, s>{});
-                nbg += T(m) * ((from_store<P>(src[pg_off + o2], ph, g) -
-                                T(6) * from_store<P>(src[pg_off + o1], ph, g)) +
-                               T(2) * from_store<P>(src[pg_off + oa], ph, g));
-                nbh += T(m) * ((from_store<P>(src[ph_off + o2], ph, g) -
-                                T(6) * from_store<P>(src[ph_off + o1], ph, g)) +
-                               T(2) * from_store<P>(src[ph_off + oa], ph, g));
+                using M2 = std::integral_constant<int, -2 * s>;
+                using M1 = std::integral_constant<int, -s>;
+                using P1 = std::integral_constant<int, s>;
+                nbg += T(m) * ((from_store<P>(at(G{}, A, M2{}), ph, g) -
+                                T(6) * from_store<P>(at(G{}, A, M1{}), ph, g)) +
+                               T(2) * from_store<P>(at(G{}, A, P1{}), ph, g));
+                nbh += T(m) * ((from_store<P>(at(H{}, A, M2{}), ph, g) -
+                                T(6) * from_store<P>(at(H{}, A, M1{}), ph, g)) +
+                               T(2) * from_store<P>(at(H{}, A, P1{}), ph, g));
             }
         });
         const T ng = xg - cs * nbg;
         const T nh = xh - cs * nbh;
+        const size_t pg_off = (size_t)(2 * i) * N, ph_off = pg_off + N;
         store_at(reinterpret_cast<char*>(dst + pg_off), (uint32_t)(cell * sizeof(S)),
                  to_store<P>(ng, ph, g));
         store_at(reinterpret_cast<char*>(dst + ph_off), (uint32_t)(cell * sizeof(S)),
@@ -336,26 +341,215 @@ __global__ __launch_bounds__(256) void k_fd_update(const void* __restrict__ src_
             if constexpr (V.qn[g] != 0) ae += T(V.qn[g]) * ng;
             ah += nh;
         }
+    }
+
+    // Running sums: the first chunk starts them, the last turns the totals
+    // into the next step's record (this lane has read its cell's record).
+    __device__ __forceinline__ void finish(T* __restrict__ rec, int64_t N, int64_t cell,
+                                           const Physics& ph) {
+        if constexpr (ACC) {
+            T* acc = rec + (size_t)kRecFields<D, DEV> * N;
+            T sums[6] = {a0, ax, ay, az, ae, ah};
+            constexpr int kSlots[6] = {0, 1, 2, D == 3 ? 3 : -1, D + 1, D + 2};
+            if constexpr (C0 != 0) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k)
+                    if (kSlots[k] >= 0) sums[k] += acc[(size_t)kSlots[k] * N + cell];
+            }
+            if constexpr (C1 == VelSet<D>::Q) {
+                write_record<D, P>(sums[0], sums[1], sums[2], sums[3], sums[4], sums[5], rec, N,
+                                   cell, ph);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 6; ++k)
+                    if (kSlots[k] >= 0) acc[(size_t)kSlots[k] * N + cell] = sums[k];
+            }
+        }
+    }
+};
+
+// Update of populations [C0, C1) of every cell, one lane per cell, the
+// stencil values read straight from global memory (through L1/L2).
+template <int D, class P, int C0, int C1>
+__global__ __launch_bounds__(256) void k_fd_update(const void* __restrict__ src_v,
+                                                   void* __restrict__ dst_v,
+                                                   typename P::T* __restrict__ rec,
+                                                   const StepArgs a) {
+    using S = typename P::S;
+    const int64_t N = a.N;
+    int xt, cy, cz;
+    if (!sweep_tile(a, (int)blockIdx.x, xt, cy, cz)) return;
+    const int cx = xt * 256 + (int)threadIdx.x;
+    if (cx >= a.nx) return;
+    const int64_t cell = (int64_t)cx + (int64_t)a.nx * cy + (int64_t)a.nxy * cz;
+    const Physics& ph = a.ph;
+    PullTable<D> pt;  // pt.src for shift e gives the cell at x - e (wrapped or clamped)
+    pt.fill(cx, cy, cz, a.nx, a.ny, a.nz, a.nxy, a.open_end, true);
+    const S* src = static_cast<const S*>(src_v);
+    S* dst = static_cast<S*>(dst_v);
+    FdCell<D, P, C0, C1> c;
+    c.load(rec, N, cell, ph);
+    static_for<C0, C1>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        // offset of the neighbour x + d along axis ax of this cell
+        auto at = [&](auto Dist, auto Ax, auto Dd) {
+            constexpr int ax = decltype(Ax)::value;
+            constexpr int d = decltype(Dd)::value;
+            constexpr int dist = decltype(Dist)::value;
+            int o = ax == 0 ? pt.x[3 - d] : pt.x[3];
+            o += ax == 1 ? pt.y[3 - d] : pt.y[3];
+            if constexpr (D == 3) o += ax == 2 ? pt.z[3 - d] : pt.z[3];
+            return src[(size_t)(2 * i + dist) * N + o];
+        };
+        c.template update<i>(ph, at, dst, N, cell);
     });
-    if constexpr (!ACC) return;
-    // running sums: the first chunk starts them, the last turns the totals
-    // into the next step's record (this lane has read its cell's record)
-    T* acc = rec + (size_t)kRecFields<D, DEV> * N;
-    T sums[6] = {a0, ax, ay, az, ae, ah};
-    constexpr int kSlots[6] = {0, 1, 2, D == 3 ? 3 : -1, D + 1, D + 2};
-    if constexpr (C0 != 0) {
+    c.finish(rec, N, cell, ph);
+}
+
+// LDS-staged update, for rows of whole tiles (nx a multiple of 256).  The
+// one-lane-per-cell kernel issues a 4-byte load per stencil point, about
+// eight per population and cell, and the vector memory address unit (one
+// instruction at a time per CU), not HBM, bounds it.  Here a workgroup
+// serves one 256-cell tile and, per population, loads the rows its
+// stencils read -- the tile's own row with two cells of halo either side,
+// and the three upwind-biased rows along y and along z where the population
+// moves along them -- four cells a lane (one 16-byte load per row and wave
+// in FP32), stages them in LDS, and each lane takes its cell's stencil
+// values from there.  The arithmetic is FdCell's, as in k_fd_update.
+//
+// LDS per population: the centre rows of g and h (264 slots each: two
+// unused, two halo, 256 cells, two halo, two unused, so the cells start at a
+// 16-byte boundary), then up to 12 neighbour rows of 256 (3 per moving axis
+// y, z and per distribution).
+template <int D>
+constexpr int kLdsCentre = 264;
+template <int D>
+constexpr int kLdsSlots = 2 * kLdsCentre<D> + (D == 3 ? 12 : 6) * 256;
+
+template <int D, class P, int C0, int C1>
+__global__ __launch_bounds__(256) void k_fd_update_lds(const void* __restrict__ src_v,
+                                                       void* __restrict__ dst_v,
+                                                       typename P::T* __restrict__ rec,
+                                                       const StepArgs a) {
+    using S = typename P::S;
+    typedef S S4 __attribute__((ext_vector_type(4)));
+    constexpr VelSet<D> V = kVelSet<D>;
+    constexpr int CW = kLdsCentre<D>;
+    __shared__ __attribute__((aligned(16))) S lds[kLdsSlots<D>];
+    const int64_t N = a.N;
+    int xt, cy, cz;
+    // the whole workgroup leaves together (it meets at barriers below)
+    if (!sweep_tile(a, (int)blockIdx.x, xt, cy, cz)) return;
+    const int tid = (int)threadIdx.x;
+    // wave-uniform, in a scalar register: the row loads below branch on it
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int x0 = xt * 256;
+    const int64_t cell = (int64_t)(x0 + tid) + (int64_t)a.nx * cy + (int64_t)a.nxy * cz;
+    const Physics& ph = a.ph;
+    const bool open_x = a.open_end & 1u, open_y = a.open_end & 2u, open_z = a.open_end & 4u;
+    // starts (cells) of the tile's part of its own row and of rows y + d and
+    // z + d, d = -2, -1, 1, 2: wave-uniform, computed once
+    const int64_t own = (int64_t)a.nx * cy + (int64_t)a.nxy * cz + x0;
+    int64_t ys[4], zs[4];
 #pragma unroll
-        for (int k = 0; k < 6; ++k)
-            if (kSlots[k] >= 0) sums[k] += acc[(size_t)kSlots[k] * N + cell];
+    for (int k = 0; k < 4; ++k) {
+        const int d = k < 2 ? k - 2 : k - 1;
+        ys[k] = own + (int64_t)(pull_coord(cy, -d, a.ny, open_y) - cy) * a.nx;
+        zs[k] = D == 3 ? own + (int64_t)(pull_coord(cz, -d, a.nz, open_z) - cz) * a.nxy : own;
     }
-    if constexpr (C1 == VelSet<D>::Q) {
-        write_record<D, P>(sums[0], sums[1], sums[2], sums[3], sums[4], sums[5], rec, N, cell,
-                           ph);
-    } else {
+    // halo cells x0 - 2, x0 - 1, x0 + 256, x0 + 257 of the tile's row (lanes 0..3)
+    const int hsh = lane < 2 ? 2 - lane : -254 - lane;  // pull shift e: source x0 - e
+    const int64_t halo_src = (int64_t)pull_coord(x0, hsh, a.nx, open_x) - x0;
+    const int halo_slot = lane < 2 ? 2 + lane : 258 + lane;  // slots 2, 3, 260, 261
+    const S* src = static_cast<const S*>(src_v);
+    S* dst = static_cast<S*>(dst_v);
+    // Rows of population i: 0, 1 the g and h centre rows; then per moving
+    // axis (y first) and distribution the rows at -2s, -s, +s.  Wave w
+    // loads rows w, w + 4, w + 8, w + 12, picked branch-free; the loads of
+    // the next population are issued before this one is computed, and land
+    // in LDS after the barrier that ends this one's reads.
+    S4 q[4];
+    int slot[4];
+    bool has[4];
+    S hv = S(0);
+    bool halo = false;
+    auto issue = [&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr Vel v = V.v[i];
+        constexpr bool my = v.y != 0, mz = D == 3 && v.z != 0;
+        constexpr int sy = v.y > 0 ? 1 : -1, sz = v.z > 0 ? 1 : -1;
+        constexpr int nrows = 2 + 6 * ((my ? 1 : 0) + (mz ? 1 : 0));
+        // row r: its start in global memory and its LDS slot
+        auto row_of = [&](auto R, const S*& ptr, int& sl) {
+            constexpr int r = decltype(R)::value;
+            if constexpr (r < 2) {
+                ptr = src + (size_t)(2 * i + r) * N + own;
+                sl = r * CW + 4;
+            } else {
+                constexpr int k = (r - 2) % 3;         // -2s, -s, +s
+                constexpr int dist = ((r - 2) / 3) % 2;
+                constexpr bool along_y = my && (r - 2) < 6;
+                constexpr int sg = along_y ? sy : sz;
+                constexpr int d = k == 0 ? -2 * sg : (k == 1 ? -sg : sg);
+                constexpr int kk = d < 0 ? d + 2 : d + 1;  // index in ys / zs
+                ptr = src + (size_t)(2 * i + dist) * N + (along_y ? ys[kk] : zs[kk]);
+                sl = 2 * CW + (r - 2) * 256;
+            }
+        };
+        static_for<0, 4>([&](auto M) {
+            constexpr int m = decltype(M)::value;
+            const S* ptr = nullptr;
+            int sl = 0;
+            static_for<0, 4>([&](auto W) {
+                constexpr int r = 4 * m + decltype(W)::value;
+                if constexpr (r < nrows) {
+                    const S* p;
+                    int sr;
+                    row_of(std::integral_constant<int, r>{}, p, sr);
+                    ptr = wave == decltype(W)::value ? p : ptr;
+                    sl = wave == decltype(W)::value ? sr : sl;
+                }
+            });
+            has[m] = 4 * m + 3 < nrows || ptr != nullptr;
+            slot[m] = sl;
+            if (has[m]) q[m] = *reinterpret_cast<const S4*>(ptr + 4 * lane);
+        });
+        // the halo of the centre row of distribution = wave (waves 0, 1)
+        halo = v.x != 0 && wave < 2 && lane < 4;
+        if (halo) hv = src[(size_t)(2 * i + wave) * N + own + halo_src];
+    };
+    FdCell<D, P, C0, C1> c;
+    c.load(rec, N, cell, ph);
+    issue(std::integral_constant<int, C0>{});
+    static_for<C0, C1>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr Vel v = V.v[i];
+        constexpr bool my = v.y != 0;
+        constexpr int sy = v.y > 0 ? 1 : -1, sz = v.z > 0 ? 1 : -1;
+        if constexpr (i != C0) __syncthreads();  // the previous population's reads are done
 #pragma unroll
-        for (int k = 0; k < 6; ++k)
-            if (kSlots[k] >= 0) acc[(size_t)kSlots[k] * N + cell] = sums[k];
-    }
+        for (int m = 0; m < 4; ++m)
+            if (has[m]) *reinterpret_cast<S4*>(lds + slot[m] + 4 * lane) = q[m];
+        if (halo) lds[wave * CW + halo_slot] = hv;
+        __syncthreads();
+        if constexpr (i + 1 < C1) issue(std::integral_constant<int, i + 1>{});
+        auto at = [&](auto Dist, auto Ax, auto Dd) {
+            constexpr int dist = decltype(Dist)::value;
+            constexpr int ax = decltype(Ax)::value;
+            constexpr int d = decltype(Dd)::value;
+            if constexpr (d == 0 || ax == 0) {
+                return lds[dist * CW + 4 + tid + d];
+            } else {
+                constexpr int s = ax == 1 ? sy : sz;
+                constexpr int k = d == -2 * s ? 0 : (d == -s ? 1 : 2);
+                constexpr int blk = (ax == 2 && my) ? 2 : 0;  // y's rows come first
+                return lds[2 * CW + (3 * (blk + dist) + k) * 256 + tid];
+            }
+        };
+        c.template update<i>(ph, at, dst, N, cell);
+    });
+    c.finish(rec, N, cell, ph);
 }
 
 template <int D, class P, int C>
@@ -363,8 +557,14 @@ hipError_t launch_chunks(const StepArgs& a, typename P::T* rec, int grid, hipStr
     if constexpr (C == chunk_count<D>()) {
         return hipSuccess;
     } else {
-        hipError_t e = launch_kernel(&k_fd_update<D, P, chunk_begin<D>(C), chunk_end<D>(C)>,
-                                     dim3(grid), dim3(256), s, a.src, a.dst, rec, a);
+        // rows of whole tiles: the LDS-staged kernel (its 16-byte row loads
+        // need every row to start on a tile boundary)
+        constexpr int c0 = chunk_begin<D>(C), c1 = chunk_end<D>(C);
+        hipError_t e = a.nx % 256 == 0
+                           ? launch_kernel(&k_fd_update_lds<D, P, c0, c1>, dim3(grid), dim3(256),
+                                           s, a.src, a.dst, rec, a)
+                           : launch_kernel(&k_fd_update<D, P, c0, c1>, dim3(grid), dim3(256), s,
+                                           a.src, a.dst, rec, a);
         if (e != hipSuccess) return e;
         return launch_chunks<D, P, C + 1>(a, rec, grid, s);
     }
@@ -387,7 +587,7 @@ hipError_t fd_two_pass_impl(const StepArgs& a0, void* rec_v, bool record_valid, 
         if (e != hipSuccess) return e;
     }
     // one x-row tile of one chunk's planes (at most 14 populations, g and h)
-    const int64_t tile_bytes = 256LL * 2 * kChunkW * (int64_t)sizeof(typename P::S);
+    const int64_t tile_bytes = 256LL * 2 * kChunkW<D> * (int64_t)sizeof(typename P::S);
     a.tiles_per_row = (a.nx + 255) / 256;
     int64_t budget = kFdWindowBytes / (5 * tile_bytes);  // tiles in a reuse window
     if (budget < 1) budget = 1;

@@ -184,3 +184,62 @@ def test_fd_full_size_sampled_cells(dim):
         worst[2] = max(worst[2], abs(T[cell] - T_o) / T_o)
     print(f"\nPARITY FD full-size D{dim} FP32 sampled rho/u/T={worst}")
     assert max(worst) <= TOL_FP32, worst
+
+
+def _tile_x(fields, shape, times):
+    """Fields of a grid repeated ``times`` over x (flat arrays, x fastest)."""
+    nx, ny, nz = shape
+    rho, u, T = fields
+    rep = lambda a: np.concatenate([a.reshape(nz, ny, nx)] * times, axis=-1).reshape(-1)
+    return rep(rho), np.stack([rep(c) for c in u]), rep(T)
+
+
+@pytest.mark.parametrize("dim,shape,bc", [
+    (3, (128, 6, 5), lbm.LBM_BC(0, 1, 0)), (3, (128, 4, 7), lbm.LBM_BC(0, 0, 1)),
+    (2, (128, 9, 1), lbm.LBM_BC(0, 1)), (2, (256, 5, 1), 0)])
+@pytest.mark.parametrize("precision,tol", [(P64, TOL_FP64), (P32, TOL_FP32)])
+def test_fd_lds_kernel_against_per_cell_kernel(dim, shape, bc, precision, tol):
+    """Rows of whole 256-cell tiles take the LDS-staged update kernel, other
+    widths the one-lane-per-cell kernel; both run FdCell's per-cell steps.
+    Two periodic copies of a grid along x, run on the doubled grid (LDS
+    kernel), must give each copy the original grid's state (per-cell kernel
+    when its width is 128; 256 -> 512 compares the LDS kernel with itself
+    across tile boundaries, bitwise).  Between the two kernels the compiler
+    fuses multiply-adds differently (it contracts per basic block), so they
+    agree to rounding: the parity bars, far below a wrong stencil value."""
+    dt = 0.25 / (3 * R)
+    f = smooth_fields(dim, *shape, seed=17, a_rho=0.05, a_u=0.05, a_T=0.05)
+    wide = (2 * shape[0], shape[1], shape[2])
+    a = gpu_run(dim, 1.4, 0.1, 0.12, shape, f, 25, bc=bc, precision=precision, dt=dt,
+                variant=TWO)
+    b = gpu_run(dim, 1.4, 0.1, 0.12, wide, _tile_x(f, shape, 2), 25, bc=bc,
+                precision=precision, dt=dt, variant=TWO)
+    nx, ny, nz = shape
+    halves = []
+    for k in range(2):
+        halves.append([y.reshape(-1, nz, ny, 2 * nx)[..., k * nx:(k + 1) * nx].reshape(y.shape[:-1] + (-1,))
+                       for y in b[:3]])
+    for h in halves:
+        e = assert_close(h, a, tol, f"LDS vs per-cell kernel {shape} bc={bc}")
+    print(f"\nFD LDS vs per-cell {shape} bc={bc} precision={precision}: rho/u/T {e}")
+    if shape[0] % 256 == 0:  # the same kernel on both grids
+        for x, y in zip(a[:3], halves[0]):
+            assert np.array_equal(x, y)
+    for x, y in zip(halves[0], halves[1]):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("dim,shape,bc", [
+    (3, (256, 5, 3), lbm.LBM_BC(1, 0, 1)), (3, (256, 3, 4), lbm.LBM_BC(0, 1, 0)),
+    (2, (512, 7, 1), lbm.LBM_BC(1, 0)), (2, (256, 2, 1), 0)])
+@pytest.mark.parametrize("precision,tol", [(P64, TOL_FP64), (P32, TOL_FP32)])
+def test_fd_lds_kernel_against_oracle(dim, shape, bc, precision, tol):
+    """The LDS-staged update (rows of whole tiles) with open and periodic
+    ends, and rows of two tiles whose halos come from the neighbour tile."""
+    dt = 0.25 / (3 * R)
+    f = smooth_fields(dim, *shape, seed=19, a_rho=0.05, a_u=0.05, a_T=0.05)
+    o = oracle_run(dim, 1.4, 0.1, 0.12, shape, f, 20, open_end=open_of(bc), dt=dt)
+    g = gpu_run(dim, 1.4, 0.1, 0.12, shape, f, 20, bc=bc, precision=precision, dt=dt,
+                variant=TWO)
+    e = assert_close(g, o, tol, f"FD LDS {shape} bc={bc}")
+    print(f"\nPARITY FD LDS {shape} bc={bc} precision={precision} rho/u/T={e}")
