@@ -243,3 +243,25 @@ def test_fd_lds_kernel_against_oracle(dim, shape, bc, precision, tol):
                 variant=TWO)
     e = assert_close(g, o, tol, f"FD LDS {shape} bc={bc}")
     print(f"\nPARITY FD LDS {shape} bc={bc} precision={precision} rho/u/T={e}")
+
+
+_LDS_1000 = {}
+
+
+@pytest.mark.parametrize("dim,shape", [(2, (256, 12, 1)), (3, (256, 6, 4))])
+@pytest.mark.parametrize("precision,tol", [(P64, TOL_FP64), (P32, TOL_FP32)])
+def test_fd_lds_kernel_1000_steps(dim, shape, precision, tol):
+    """The LDS-staged update over 1000 steps, against the oracle."""
+    c = CASE2D if dim == 2 else CASE3D
+    if dim == 2:
+        f = smooth_fields(2, *shape, seed=2, kmax=1)
+    else:
+        f = shear_wave_fields(3, *shape, seed=3)
+    if dim not in _LDS_1000:  # one oracle run per grid
+        _LDS_1000[dim] = oracle_run(dim, c["gamma"], c["tf"], c["tg"], shape, f, 1000,
+                                    dt=c["dt"])
+    o = _LDS_1000[dim]
+    g = gpu_run(dim, c["gamma"], c["tf"], c["tg"], shape, f, 1000, precision=precision,
+                variant=TWO, dt=c["dt"])
+    e = assert_close(g, o, tol, f"FD LDS {shape} 1000 steps")
+    print(f"\nPARITY FD LDS {shape} 1000 steps precision={precision} rho/u/T={e}")
