@@ -166,11 +166,14 @@ int lbm_set_stream(lbm_handle h, void *stream);
  *             lane l + 32 of the wave;
  *   TWO_PASS  (lbm_create_fd solves only) the finite-difference step as a
  *             moments pass plus updates of chunks of populations, which
- *             keeps each chunk's neighbour rows in cache;
+ *             keeps each chunk's neighbour rows in cache; where nx is a
+ *             multiple of 256 the updates stage each population's stencil
+ *             rows in LDS (same results to rounding);
  *   AUTO      (the default) lattice streaming: LANE for D2Q37, SPLIT for
  *             D3Q107, whose 214 populations do not fit one lane's
  *             registers; finite differences: TWO_PASS, except LANE for
- *             D2Q37 in FP64, where the fused kernel is faster.
+ *             D2Q37 in FP64 when nx is not a multiple of 256, where the
+ *             fused kernel is faster than the two-pass step without LDS.
  * EINVAL for other values, and for TWO_PASS on a lattice-streaming solve. */
 enum lbm_variant {
     LBM_VARIANT_AUTO = 0,

@@ -128,11 +128,14 @@ int create_solver(int dim, int velocity_set, double gamma, double tau_f, double 
                   lbm_handle* out);
 
 // Finite differences, AUTO variant: the two-pass step, except for D2Q37 in
-// FP64, where the fused kernel's neighbour rows still fit the L2 and it
-// streams faster (measured on 4096^2: 5.9 ms fused, 8.7 ms two-pass; FP32
-// 4.7 and 3.9 ms; D3Q107 FP32 31.7 and 12.8 ms).
-bool fd_fused_by_default(int dim, int precision) {
-    return dim == 2 && precision == LBM_FP64;
+// FP64 on rows that are not whole 256-cell tiles.  There the fused kernel's
+// neighbour rows still fit the L2 and it streams faster than the two-pass
+// step with its one-lane update kernel (measured on 4096^2: 5.9 ms fused,
+// 8.7 ms two-pass with that kernel); with the LDS-staged update the
+// two-pass step is faster (5.4 ms).  D3Q107 FP32 256^3: 31.7 ms fused,
+// 10.3 ms two-pass.
+bool fd_fused_by_default(int dim, int precision, int64_t nx) {
+    return dim == 2 && precision == LBM_FP64 && nx % 256 != 0;
 }
 
 }  // namespace
@@ -248,7 +251,7 @@ int create_solver(int dim, int velocity_set, double gamma, double tau_f, double 
     // one lane per cell keeps all 2Q populations in registers; for D3Q107
     // that is 214 values, so the 3D kernels split g and h across lane pairs
     h->split = dim == 3;
-    h->fd_fused = fd_fused_by_default(dim, precision);
+    h->fd_fused = fd_fused_by_default(dim, precision, nx);
     hipError_t e = hipGetDevice(&h->device);
     if (e != hipSuccess) {
         delete h;
@@ -306,7 +309,7 @@ int lbm_set_variant(lbm_handle h, int variant) {
     switch (variant) {
         case LBM_VARIANT_AUTO:
             h->split = h->dim == 3;
-            h->fd_fused = fd_fused_by_default(h->dim, h->precision);
+            h->fd_fused = fd_fused_by_default(h->dim, h->precision, h->nx);
             return LBM_OK;
         case LBM_VARIANT_LANE: h->split = false; h->fd_fused = true; return LBM_OK;
         case LBM_VARIANT_SPLIT: h->split = true; h->fd_fused = true; return LBM_OK;

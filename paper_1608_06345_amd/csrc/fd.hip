@@ -20,8 +20,8 @@
 //                 from global memory (k_fd_update).  Each pass also adds its
 //                 new populations' moment sums into a per-cell accumulator,
 //                 and the last one turns the totals into the next step's
-//                 record, so in FP32 the moments pass runs only after the
-//                 state was set from outside (init).
+//                 record, so the moments pass runs only after the state
+//                 was set from outside (init) or by a fused step.
 //
 // The arithmetic is that of the fused kernel: the same equilibrium, the
 // same target sums for the correction (accumulated in the same order), the
@@ -42,14 +42,13 @@ using namespace core;
 template <int D, bool DEV>
 constexpr int kRecFields = DEV ? 2 * D + 6 : D + 3;
 // After the record: the running moment sums of the new state, s0, sj (D),
-// se and sh (sum of h), accumulated chunk by chunk.  Only in FP32 deviation
-// storage: in FP64 the accumulator's read-modify-write per chunk (96 B per
-// cell) costs more than the moments pass it saves (D3Q107 256^3: 32.0 ms
-// against 30.4 ms per step), so FP64 runs the moments pass every step.
+// se and sh (sum of h), accumulated chunk by chunk.  Its read-modify-write
+// per chunk (48 B per cell in FP64) costs less than the moments pass it
+// saves, a read of every population: D3Q107 256^3 FP64 19.7 ms against 23.3
+// ms per step with the six chunks below (with 8 narrower chunks and the
+// one-lane update kernel it was the other way round, 32.0 against 30.4).
 template <int D>
 constexpr int kAccFields = D + 3;
-template <class P>
-constexpr bool kAccumulate = !std::is_same_v<P, F64>;
 
 // Population chunks of the update passes: the rest and axis populations
 // (which take the correction) with the first pairs, then 21 at a time in 3D
@@ -221,7 +220,6 @@ struct FdCell {
     using T = typename P::T;
     using S = typename P::S;
     static constexpr bool DEV = P::kDev;
-    static constexpr bool ACC = kAccumulate<P>;
     Equilibrium<D, T, DEV> eq;
     T rho, arho_h, beta_g, beta_h, omf, omg, cs;
     T dm = 0, de = 0, dmh = 0, dj[3] = {0, 0, 0};
@@ -333,7 +331,7 @@ struct FdCell {
                  to_store<P>(ng, ph, g));
         store_at(reinterpret_cast<char*>(dst + ph_off), (uint32_t)(cell * sizeof(S)),
                  to_store<P>(nh, ph, g));
-        if constexpr (ACC) {
+        {
             a0 += ng;
             if constexpr (v.x != 0) ax += T(v.x) * ng;
             if constexpr (v.y != 0) ay += T(v.y) * ng;
@@ -347,7 +345,7 @@ struct FdCell {
     // into the next step's record (this lane has read its cell's record).
     __device__ __forceinline__ void finish(T* __restrict__ rec, int64_t N, int64_t cell,
                                            const Physics& ph) {
-        if constexpr (ACC) {
+        {
             T* acc = rec + (size_t)kRecFields<D, DEV> * N;
             T sums[6] = {a0, ax, ay, az, ae, ah};
             constexpr int kSlots[6] = {0, 1, 2, D == 3 ? 3 : -1, D + 1, D + 2};
@@ -581,7 +579,7 @@ hipError_t fd_two_pass_impl(const StepArgs& a0, void* rec_v, bool record_valid, 
     StepArgs a = a0;
     T* rec = static_cast<T*>(rec_v);
     const int tiles = (int)((a.N + 255) / 256);
-    if (!record_valid || !kAccumulate<P>) {
+    if (!record_valid) {
         hipError_t e = launch_kernel(&k_fd_moments<D, P>, dim3(tiles), dim3(256), s, a.src, rec,
                                      a.N, a.ph);
         if (e != hipSuccess) return e;
@@ -617,9 +615,9 @@ hipError_t fd_two_pass_impl(const StepArgs& a0, void* rec_v, bool record_valid, 
 }  // namespace
 
 size_t fd_record_bytes(int dim, int precision, int64_t N) {
-    const bool dev = precision != LBM_FP64;  // deviation storage: record + accumulator
-    const int fields = dim == 2 ? (dev ? kRecFields<2, true> + kAccFields<2> : kRecFields<2, false>)
-                                : (dev ? kRecFields<3, true> + kAccFields<3> : kRecFields<3, false>);
+    const bool dev = precision != LBM_FP64;  // record (deviation storage: residuals too)
+    const int fields = dim == 2 ? (dev ? kRecFields<2, true> : kRecFields<2, false>) + kAccFields<2>
+                                : (dev ? kRecFields<3, true> : kRecFields<3, false>) + kAccFields<3>;
     return (size_t)fields * (size_t)N * (precision == LBM_FP64 ? 8 : 4);
 }
 

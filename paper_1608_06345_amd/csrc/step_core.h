@@ -33,6 +33,16 @@ __device__ __forceinline__ void store_at(char* base, uint32_t byte_off, T v) {
     __builtin_nontemporal_store(v, reinterpret_cast<T*>(base + byte_off));
 }
 
+// Ordinary (cached) store.  A split-layout wave writes 32 cells of a plane;
+// in half storage that is 64 bytes, half a 128-byte line, and the other half
+// comes from the neighbouring wave.  Through the cache the halves meet in L2
+// before the line goes out (measured 4-5% faster at D3Q107 256^3 than
+// streaming them; in the lane layout, whole lines, streaming stays faster).
+template <typename T>
+__device__ __forceinline__ void store_cached(char* base, uint32_t byte_off, T v) {
+    *reinterpret_cast<T*>(base + byte_off) = v;
+}
+
 // Source coordinate of a pull along one axis: x - e, wrapped (periodic) or
 // clamped (zero gradient).
 __device__ __forceinline__ int pull_coord(int x, int e, int n, bool open_end) {
@@ -558,7 +568,11 @@ __device__ __forceinline__ void store_split(char* dst, uint32_t plane,
     char* row = dst + o.row;
     static_for<0, VelSet<D>::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        store_at(row + (size_t)(2 * i) * plane, o.own, to_store<P>(p[i], ph, V.v[i].group));
+        const auto x = to_store<P>(p[i], ph, V.v[i].group);
+        if constexpr (sizeof(typename P::S) == 2)
+            store_cached(row + (size_t)(2 * i) * plane, o.own, x);
+        else
+            store_at(row + (size_t)(2 * i) * plane, o.own, x);
     });
 }
 
