@@ -41,6 +41,11 @@ for _store in ("fp32", "fp64", "fp16"):
 for _store in ("fp32", "fp64", "fp16"):
     PATHS[f"d2q37_{_store}"] = dict(dim=2, shape=(4096, 4096, 1), gamma=1.4, tf=0.7, tg=0.8,
                                     store=_store, seed=2, steps=1000)
+# The D3Q107 step with its pulled rows staged in LDS (variant SPLIT_LDS),
+# beside the default kernel that pulls straight from global memory.
+for _store in ("fp32", "fp64", "fp16"):
+    PATHS[f"d3q107_{_store}_lds"] = dict(PATHS[f"d3q107_{_store}"], steps=200,
+                                         variant="split_lds")
 
 
 # The finite-difference form of Sec. III on the same grids and fields: time
@@ -69,6 +74,8 @@ def describe(name, p):
     grid = "x".join(str(n) for n in p["shape"][:p["dim"]])
     delta = 2.0 / (p["gamma"] - 1.0) - p["dim"]
     scheme = (f"finite-difference form, dt {p['dt']:.4f}, " if p.get("dt") else "")
+    if p.get("variant") == "split_lds":
+        scheme = "pulled rows staged in LDS, "
     return (f"D{p['dim']}Q{q} {grid} periodic, smooth seeded field (seed {p['seed']}), "
             f"{scheme}gamma {p['gamma']} (delta {delta:g}), tau_f {p['tf']}, tau_g {p['tg']}, "
             f"{STORAGE[p['store']][0]}")
@@ -114,6 +121,8 @@ def run_path(name, p, steps, warmup):
     with lbm.Solver(p["dim"], p["gamma"], p["tf"], p["tg"], nx, ny, nz, precision=prec,
                     dt=p.get("dt")) as s:
         s.set_stream(stream)
+        if p.get("variant") == "split_lds":
+            s.set_variant(lbm.LBM_VARIANT_SPLIT_LDS)
         dev = [torch.from_numpy(a.reshape(-1)).to("cuda") for a in f]
         torch.cuda.synchronize()
         lbm.lbm_init_fields_dev(s.h, *dev)

@@ -169,17 +169,24 @@ int lbm_set_stream(lbm_handle h, void *stream);
  *             keeps each chunk's neighbour rows in cache; where nx is a
  *             multiple of 256 the updates stage each population's stencil
  *             rows in LDS (same results to rounding);
+ *   SPLIT_LDS (D3Q107 lattice streaming, nx a multiple of 128) SPLIT with
+ *             the pulled rows staged in LDS: a workgroup loads each
+ *             population's shifted row once, four cells a lane, and each
+ *             lane reads its pulled value from LDS (same results to
+ *             rounding);
  *   AUTO      (the default) lattice streaming: LANE for D2Q37, SPLIT for
  *             D3Q107, whose 214 populations do not fit one lane's
  *             registers; finite differences: TWO_PASS, except LANE for
  *             D2Q37 in FP64 when nx is not a multiple of 256, where the
  *             fused kernel is faster than the two-pass step without LDS.
- * EINVAL for other values, and for TWO_PASS on a lattice-streaming solve. */
+ * EINVAL for other values, for TWO_PASS on a lattice-streaming solve, and for
+ * SPLIT_LDS on any other solve. */
 enum lbm_variant {
     LBM_VARIANT_AUTO = 0,
     LBM_VARIANT_LANE = 1,
     LBM_VARIANT_SPLIT = 2,
-    LBM_VARIANT_TWO_PASS = 3
+    LBM_VARIANT_TWO_PASS = 3,
+    LBM_VARIANT_SPLIT_LDS = 4
 };
 int lbm_set_variant(lbm_handle h, int variant);
 

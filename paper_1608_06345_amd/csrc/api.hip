@@ -251,6 +251,7 @@ int create_solver(int dim, int velocity_set, double gamma, double tau_f, double 
     // one lane per cell keeps all 2Q populations in registers; for D3Q107
     // that is 214 values, so the 3D kernels split g and h across lane pairs
     h->split = dim == 3;
+    h->lds = false;
     h->fd_fused = fd_fused_by_default(dim, precision, nx);
     hipError_t e = hipGetDevice(&h->device);
     if (e != hipSuccess) {
@@ -310,12 +311,27 @@ int lbm_set_variant(lbm_handle h, int variant) {
         case LBM_VARIANT_AUTO:
             h->split = h->dim == 3;
             h->fd_fused = fd_fused_by_default(h->dim, h->precision, h->nx);
+            h->lds = false;
             return LBM_OK;
-        case LBM_VARIANT_LANE: h->split = false; h->fd_fused = true; return LBM_OK;
-        case LBM_VARIANT_SPLIT: h->split = true; h->fd_fused = true; return LBM_OK;
+        case LBM_VARIANT_LANE:
+            h->split = false;
+            h->fd_fused = true;
+            h->lds = false;
+            return LBM_OK;
+        case LBM_VARIANT_SPLIT:
+            h->split = true;
+            h->fd_fused = true;
+            h->lds = false;
+            return LBM_OK;
         case LBM_VARIANT_TWO_PASS:
             if (!h->scheme) return LBM_EINVAL;
             h->fd_fused = false;
+            h->lds = false;
+            return LBM_OK;
+        case LBM_VARIANT_SPLIT_LDS:
+            if (h->scheme || h->dim != 3 || h->nx % 128 != 0) return LBM_EINVAL;
+            h->split = true;
+            h->lds = true;
             return LBM_OK;
         default: return LBM_EINVAL;
     }
@@ -390,7 +406,9 @@ int lbm_step(lbm_handle h, int64_t n) {
             LBM_HIP(lbm::launch_fd_two_pass(h->dim, h->precision, a, h->fd_record,
                                             h->fd_record_valid, h->stream));
             h->fd_record_valid = true;
-        } else
+        } else if (h->lds)
+            LBM_HIP(lbm::launch_step_lds(h->precision, a, h->stream));
+        else
             LBM_HIP(lbm::launch_step(h->dim, h->precision, h->split, a, h->stream));
         h->cur ^= 1;
         h->initial = false;

@@ -116,6 +116,120 @@ void k_step_split(const StepArgs a) {
     store_split<D, P>(static_cast<char*>(a.dst), plane, o, p, a.ph);
 }
 
+// Fused step, split layout, with the pulled rows staged in LDS (D3Q107;
+// rows of whole 128-cell tiles).  A workgroup serves one 128-cell tile of a
+// row, its four waves 32 cells each as in k_step_split.  The pull of
+// population i reads the tile's row shifted by e_i: row (y - e_y, z - e_z),
+// cells x0 - e_x ..  x0 - e_x + 127.  Instead of one 4-byte (or 2-byte) load
+// per lane and population, the workgroup loads that row once with 4-cell
+// loads per lane -- lanes 0..31 the g row, lanes 32..63 the h row, one
+// instruction per population -- plus up to three halo cells either side,
+// stages it in LDS, and each lane takes its cell's pulled value from there.
+// Populations go through LDS in batches of kLdsBatch; the next batch's loads
+// are issued before the current one is read back.  Collision and store are
+// k_step_split's.
+constexpr int kLdsBatch = 16;
+constexpr int kLdsRow = 136;  // slots per staged row: 4 (3 halo), 128 cells, 4 (3 halo)
+
+template <class P, int WAVES>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
+void k_step_split_lds(const StepArgs a) {
+    constexpr int D = 3;
+    using T = typename P::T;
+    using S = typename P::S;
+    typedef S S4 __attribute__((ext_vector_type(4)));
+    constexpr VelSet<D> V = kVelSet<D>;
+    constexpr int Q = VelSet<D>::Q;
+    __shared__ __attribute__((aligned(16))) S lds[kLdsBatch * 2 * kLdsRow];
+    // workgroup b: turn j = b / 8 on XCD b % 8 walks whole rows (as row_item)
+    const int b = (int)blockIdx.x;
+    const int j = b >> 3;
+    const int row = (j / a.tiles_per_row) * 8 + (b & 7);
+    if (row >= a.rows) return;  // the whole workgroup
+    const int tile = j % a.tiles_per_row;
+    const int y = row % a.ny, z = row / a.ny;
+    const int x0 = tile * 128;
+    const int tid = (int)threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int role = lane >> 5;  // 0: g, 1: h
+    const int c = wave * 32 + (lane & 31);  // the lane's cell in the tile
+    const bool open_x = a.open_end & 1u, open_y = a.open_end & 2u, open_z = a.open_end & 4u;
+    const int64_t N = a.N;
+    const S* src = static_cast<const S*>(a.src);
+    // halo lanes (k = lane & 31 < 6): cells x0 - 3 .. x0 - 1, x0 + 128 .. x0 + 130
+    const int hk = lane & 31;
+    const int hshift = hk < 3 ? 3 - hk : -125 - hk;  // pull shift e: source x0 - e
+    const int hx = pull_coord(x0, hshift, a.nx, open_x);
+    const int hslot = hk < 3 ? 1 + hk : 129 + hk;  // slots 1..3, 132..134
+    // Batch loads: wave w takes the batch's populations w, w + 4, ...
+    S4 q[kLdsBatch / 4];
+    S hv[kLdsBatch / 4];
+    auto issue = [&](auto Bt) {
+        constexpr int b0 = decltype(Bt)::value * kLdsBatch;
+        static_for<0, kLdsBatch / 4>([&](auto M) {
+            constexpr int m = decltype(M)::value;
+            // population of this slot for each wave, picked branch-free
+            int64_t start = 0;
+            bool has = false, hx_need = false;
+            static_for<0, 4>([&](auto W) {
+                constexpr int i = b0 + 4 * m + decltype(W)::value;
+                if constexpr (i < Q) {
+                    constexpr Vel v = V.v[i];
+                    const int64_t st =
+                        (int64_t)(2 * i) * N +
+                        (int64_t)pull_coord(y, v.y, a.ny, open_y) * a.nx +
+                        (int64_t)pull_coord(z, v.z, a.nz, open_z) * a.nxy;
+                    const bool w = wave == decltype(W)::value;
+                    start = w ? st : start;
+                    has = w ? true : has;
+                    hx_need = w ? (v.x != 0) : hx_need;
+                }
+            });
+            hv[m] = S(0);
+            if (has) {
+                const S* rowp = src + start + (role ? N : 0);
+                q[m] = *reinterpret_cast<const S4*>(rowp + x0 + 4 * (lane & 31));
+                if (hx_need && hk < 6) hv[m] = rowp[hx];
+            }
+        });
+    };
+    T p[Q];
+    constexpr int kBatches = (Q + kLdsBatch - 1) / kLdsBatch;
+    issue(std::integral_constant<int, 0>{});
+    static_for<0, kBatches>([&](auto Bt) {
+        constexpr int bt = decltype(Bt)::value;
+        constexpr int b0 = bt * kLdsBatch;
+        if constexpr (bt != 0) __syncthreads();  // the previous batch's reads are done
+        static_for<0, kLdsBatch / 4>([&](auto M) {
+            constexpr int m = decltype(M)::value;
+            // slot of population b0 + 4 m + wave
+            const int pi = 4 * m + wave;
+            if (b0 + pi < Q) {
+                S* slot = lds + (pi * 2 + role) * kLdsRow;
+                *reinterpret_cast<S4*>(slot + 4 + 4 * (lane & 31)) = q[m];
+                if (hk < 6) slot[hslot] = hv[m];
+            }
+        });
+        __syncthreads();
+        if constexpr (bt + 1 < kBatches) issue(std::integral_constant<int, bt + 1>{});
+        static_for<0, kLdsBatch>([&](auto K) {
+            constexpr int i = b0 + decltype(K)::value;
+            if constexpr (i < Q) {
+                constexpr Vel v = V.v[i];
+                const S x = lds[(decltype(K)::value * 2 + role) * kLdsRow + 4 + c - v.x];
+                p[i] = from_store<P>(x, a.ph, v.group);
+            }
+        });
+    });
+    collide_split<D, P>(p, role, a.ph);
+    const uint32_t plane = (uint32_t)N * (uint32_t)sizeof(S);
+    RowOffsets<S> o;
+    o.row = (uint32_t)(y * a.nx + z * a.nxy) * (uint32_t)sizeof(S);
+    o.own = (uint32_t)(x0 + c) * (uint32_t)sizeof(S) + (role ? plane : 0u);
+    store_split<D, P>(static_cast<char*>(a.dst), plane, o, p, a.ph);
+}
+
 // ---------------------------------------------------------------------------
 // Initial state S_0 = equilibrium of (rho, u, T), evaluated in double and
 // stored in the storage precision (deviation from the rest equilibrium in
@@ -380,6 +494,19 @@ hipError_t launch_init(int dim, int precision, void* dst, const double* rho,
         if (dim == 2)
             return launch_kernel(&k_init<2, P>, dim3(grid), dim3(256), s, d, rho, u, T, N, half_delta, r, wg);
         return launch_kernel(&k_init<3, P>, dim3(grid), dim3(256), s, d, rho, u, T, N, half_delta, r, wg);
+    });
+}
+
+hipError_t launch_step_lds(int precision, const StepArgs& a0, hipStream_t s) {
+    StepArgs a = a0;
+    if (a.nx % 128 != 0 || !a.stream) return hipErrorInvalidValue;
+    a.rows = a.ny * a.nz;
+    a.tiles_per_row = a.nx / 128;
+    const int grid = 8 * a.tiles_per_row * ((a.rows + 7) / 8);
+    return with_policy(precision, [&](auto pol) {
+        using P = decltype(pol);
+        constexpr int kWaves = sizeof(typename P::T) == 4 ? 2 : 1;
+        return launch_kernel(&k_step_split_lds<P, kWaves>, dim3(grid), dim3(256), s, a);
     });
 }
 

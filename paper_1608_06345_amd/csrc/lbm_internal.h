@@ -108,6 +108,9 @@ hipError_t launch_init(int dim, int precision, void* dst, const double* rho,
                        const double* u, const double* T, int64_t N,
                        double half_delta, double r, const double* w_group,
                        hipStream_t s);
+// D3Q107 lattice step with the pulled rows staged in LDS (nx a multiple of
+// 128, streaming steps only; hipErrorInvalidValue otherwise).
+hipError_t launch_step_lds(int precision, const StepArgs& a, hipStream_t s);
 hipError_t launch_step(int dim, int precision, bool split, const StepArgs& a,
                        hipStream_t s);
 // One explicit finite-difference step (Sec. III); sets the wave mapping
@@ -154,6 +157,7 @@ struct lbm_solver {
     hipStream_t own_stream;
     int device;
     bool split;
+    bool lds;             // D3Q107 lattice step: pulled rows staged in LDS
     bool fd_fused;        // finite differences: one fused kernel (LANE / SPLIT variants)
     void* fd_record;      // finite differences, two passes: per-cell record
     bool fd_record_valid; // the record describes the current state

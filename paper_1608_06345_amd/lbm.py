@@ -29,6 +29,7 @@ LBM_D2Q37, LBM_D3Q107 = 37, 107
 LBM_BC_PERIODIC, LBM_BC_ZERO_GRADIENT = 0, 1
 LBM_FP64, LBM_FP32_DEV, LBM_FP16_SCALED = 0, 1, 2
 LBM_VARIANT_AUTO, LBM_VARIANT_LANE, LBM_VARIANT_SPLIT, LBM_VARIANT_TWO_PASS = 0, 1, 2, 3
+LBM_VARIANT_SPLIT_LDS = 4
 LBM_COLLISION_PAPER, LBM_COLLISION_ENERGY_CONSERVING = 0, 1
 
 
