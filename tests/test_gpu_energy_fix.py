@@ -66,6 +66,27 @@ def test_energy_fix_parity_finite_difference():
     print(f"\nPARITY energy-conserving FD D2 rho/u/T={e}")
 
 
+@pytest.mark.parametrize("dim,shape,steps", [(2, (256, 6, 1), 300), (2, (45, 38, 1), 300),
+                                              (3, (256, 4, 3), 100)])
+@pytest.mark.parametrize("precision,tol", [(lbm.LBM_FP64, TOL_FP64), (lbm.LBM_FP32_DEV, TOL_FP32)])
+def test_energy_fix_parity_finite_difference_two_pass(dim, shape, steps, precision, tol):
+    """The two-pass finite-difference step with the energy-conserving
+    collision (kappa rho in the record): the LDS-staged update kernel (rows of
+    whole 256-cell tiles) and the one-lane kernel (45 wide)."""
+    dt = (0.25 if dim == 2 else 0.3) / (3 * R)
+    tf, tg = (0.1, 0.15) if dim == 2 else (0.12, 0.16)
+    f = smooth_fields(dim, *shape, seed=8, a_rho=0.05, a_u=0.05, a_T=0.05)
+    o = _oracle(dim, 1.4, tf, tg, shape, f, steps, dt=dt)
+    with lbm.Solver(dim, 1.4, tf, tg, *shape, precision=precision, dt=dt, collision=EC) as s:
+        s.set_variant(lbm.LBM_VARIANT_TWO_PASS)
+        s.init_fields(*f)
+        s.step(steps)
+        rho, u, E = s.moments()
+        g = (rho, u, s.temperature(u, E))
+    e = assert_close(g, o, tol, f"energy fix FD two-pass {shape}")
+    print(f"\nPARITY energy-conserving FD two-pass D{dim} {shape} precision={precision} rho/u/T={e}")
+
+
 @pytest.mark.parametrize("dim,dt", [(2, None), (3, None), (2, 0.25 / (3 * R))])
 def test_energy_fix_conserves_total_energy(dim, dt):
     shape = (45, 38, 1) if dim == 2 else (21, 18, 17)
