@@ -406,14 +406,15 @@ __global__ __launch_bounds__(256) void k_fd_update(const void* __restrict__ src_
 
 // LDS-staged update, for rows of whole tiles (nx a multiple of 256).  The
 // one-lane-per-cell kernel issues a 4-byte load per stencil point, about
-// eight per population and cell, and the vector memory address unit (one
-// instruction at a time per CU), not HBM, bounds it.  Here a workgroup
-// serves one 256-cell tile and, per population, loads the rows its
-// stencils read -- the tile's own row with two cells of halo either side,
-// and the three upwind-biased rows along y and along z where the population
-// moves along them -- four cells a lane (one 16-byte load per row and wave
-// in FP32), stages them in LDS, and each lane takes its cell's stencil
-// values from there.  The arithmetic is FdCell's, as in k_fd_update.
+// eight per population and cell; its counters show the vector memory
+// address unit busy 80-98% of the time while HBM is not saturated.  Here a
+// workgroup serves one 256-cell tile and, per phase of kFdPhase
+// populations, loads the rows their stencils read -- the tile's own row
+// with two cells of halo either side, and the three upwind-biased rows
+// along y and along z where a population moves along them -- four cells a
+// lane (one 16-byte load per row and wave in FP32), stages them in LDS, and
+// each lane takes its cell's stencil values from there.  The arithmetic is
+// FdCell's, as in k_fd_update.
 //
 // LDS per population: the centre rows of g and h (264 slots each: two
 // unused, two halo, 256 cells, two halo, two unused, so the cells start at a
@@ -423,8 +424,21 @@ template <int D>
 constexpr int kLdsCentre = 264;
 template <int D>
 constexpr int kLdsSlots = 2 * kLdsCentre<D> + (D == 3 ? 12 : 6) * 256;
+// Populations staged per barrier phase: two for D3Q107 in FP32 (2% faster at
+// 256^3), one otherwise (two were 1-3.5% slower: FP64 needs twice the LDS and
+// 190-209 VGPRs, and D2Q37 rows are fewer).
+template <int D, class P>
+constexpr int kFdPhase = (D == 3 && sizeof(typename P::S) == 4) ? 2 : 1;
 
-template <int D, class P, int C0, int C1>
+// Stencil rows of population i staged per phase: the g and h centre rows,
+// then per moving axis (y first) and distribution the rows at -2s, -s, +s.
+template <int D>
+constexpr int fd_rows(int i) {
+    const Vel v = kVelSet<D>.v[i];
+    return 2 + 6 * ((v.y != 0 ? 1 : 0) + (D == 3 && v.z != 0 ? 1 : 0));
+}
+
+template <int D, class P, int C0, int C1, int PB>
 __global__ __launch_bounds__(256) void k_fd_update_lds(const void* __restrict__ src_v,
                                                        void* __restrict__ dst_v,
                                                        typename P::T* __restrict__ rec,
@@ -433,7 +447,9 @@ __global__ __launch_bounds__(256) void k_fd_update_lds(const void* __restrict__ 
     typedef S S4 __attribute__((ext_vector_type(4)));
     constexpr VelSet<D> V = kVelSet<D>;
     constexpr int CW = kLdsCentre<D>;
-    __shared__ __attribute__((aligned(16))) S lds[kLdsSlots<D>];
+    constexpr int SL = kLdsSlots<D>;  // LDS slots of one population
+    static_assert(PB == 1 || PB == 2, "one or two populations per phase");
+    __shared__ __attribute__((aligned(16))) S lds[PB * SL];
     const int64_t N = a.N;
     int xt, cy, cz;
     // the whole workgroup leaves together (it meets at barriers below)
@@ -462,28 +478,35 @@ __global__ __launch_bounds__(256) void k_fd_update_lds(const void* __restrict__ 
     const int halo_slot = lane < 2 ? 2 + lane : 258 + lane;  // slots 2, 3, 260, 261
     const S* src = static_cast<const S*>(src_v);
     S* dst = static_cast<S*>(dst_v);
-    // Rows of population i: 0, 1 the g and h centre rows; then per moving
-    // axis (y first) and distribution the rows at -2s, -s, +s.  Wave w
-    // loads rows w, w + 4, w + 8, w + 12, picked branch-free; the loads of
-    // the next population are issued before this one is computed, and land
-    // in LDS after the barrier that ends this one's reads.
-    S4 q[4];
-    int slot[4];
-    bool has[4];
+    // A phase stages PB populations.  Its rows, population by population, are
+    // numbered R = 0, 1, ...; wave w loads rows w, w + 4, ..., picked branch-
+    // free.  The next phase's loads are issued before this one is computed
+    // and land in LDS after the barrier that ends this phase's reads.  The
+    // halo of population j's distribution d is loaded by wave 2 j + d.
+    constexpr int kMaxSets = (14 * PB + 3) / 4;
+    S4 q[kMaxSets];
+    int slot[kMaxSets];
+    bool has[kMaxSets];
     S hv = S(0);
     bool halo = false;
-    auto issue = [&](auto I) {
-        constexpr int i = decltype(I)::value;
-        constexpr Vel v = V.v[i];
-        constexpr bool my = v.y != 0, mz = D == 3 && v.z != 0;
-        constexpr int sy = v.y > 0 ? 1 : -1, sz = v.z > 0 ? 1 : -1;
-        constexpr int nrows = 2 + 6 * ((my ? 1 : 0) + (mz ? 1 : 0));
-        // row r: its start in global memory and its LDS slot
-        auto row_of = [&](auto R, const S*& ptr, int& sl) {
-            constexpr int r = decltype(R)::value;
+    int halo_at = 0;
+    auto issue = [&](auto Ph) {
+        constexpr int i0 = C0 + PB * decltype(Ph)::value;
+        constexpr int np = (C1 - i0) < PB ? (C1 - i0) : PB;
+        constexpr int nr0 = fd_rows<D>(i0);
+        constexpr int nrows = nr0 + (np > 1 ? fd_rows<D>(i0 + 1) : 0);
+        // phase row R: its start in global memory and its LDS slot
+        auto row_of = [&](auto RR, const S*& ptr, int& sl) {
+            constexpr int R = decltype(RR)::value;
+            constexpr int j = R < nr0 ? 0 : 1;
+            constexpr int i = i0 + j;
+            constexpr int r = R - (j ? nr0 : 0);
+            constexpr Vel v = V.v[i];
+            constexpr bool my = v.y != 0;
+            constexpr int sy = v.y > 0 ? 1 : -1, sz = v.z > 0 ? 1 : -1;
             if constexpr (r < 2) {
                 ptr = src + (size_t)(2 * i + r) * N + own;
-                sl = r * CW + 4;
+                sl = j * SL + r * CW + 4;
             } else {
                 constexpr int k = (r - 2) % 3;         // -2s, -s, +s
                 constexpr int dist = ((r - 2) / 3) % 2;
@@ -492,20 +515,20 @@ __global__ __launch_bounds__(256) void k_fd_update_lds(const void* __restrict__ 
                 constexpr int d = k == 0 ? -2 * sg : (k == 1 ? -sg : sg);
                 constexpr int kk = d < 0 ? d + 2 : d + 1;  // index in ys / zs
                 ptr = src + (size_t)(2 * i + dist) * N + (along_y ? ys[kk] : zs[kk]);
-                sl = 2 * CW + (r - 2) * 256;
+                sl = j * SL + 2 * CW + (r - 2) * 256;
             }
         };
-        static_for<0, 4>([&](auto M) {
+        static_for<0, kMaxSets>([&](auto M) {
             constexpr int m = decltype(M)::value;
             const S* ptr = nullptr;
             int sl = 0;
             static_for<0, 4>([&](auto W) {
-                constexpr int r = 4 * m + decltype(W)::value;
-                if constexpr (r < nrows) {
-                    const S* p;
+                constexpr int R = 4 * m + decltype(W)::value;
+                if constexpr (R < nrows) {
+                    const S* pr;
                     int sr;
-                    row_of(std::integral_constant<int, r>{}, p, sr);
-                    ptr = wave == decltype(W)::value ? p : ptr;
+                    row_of(std::integral_constant<int, R>{}, pr, sr);
+                    ptr = wave == decltype(W)::value ? pr : ptr;
                     sl = wave == decltype(W)::value ? sr : sl;
                 }
             });
@@ -513,39 +536,52 @@ __global__ __launch_bounds__(256) void k_fd_update_lds(const void* __restrict__ 
             slot[m] = sl;
             if (has[m]) q[m] = *reinterpret_cast<const S4*>(ptr + 4 * lane);
         });
-        // the halo of the centre row of distribution = wave (waves 0, 1)
-        halo = v.x != 0 && wave < 2 && lane < 4;
-        if (halo) hv = src[(size_t)(2 * i + wave) * N + own + halo_src];
+        // halo: population j = wave / 2, distribution wave % 2
+        const int j = wave >> 1, dist = wave & 1;
+        constexpr bool hx0 = V.v[i0].x != 0;
+        constexpr bool hx1 = np > 1 && V.v[np > 1 ? i0 + 1 : i0].x != 0;
+        const bool need = j == 0 ? hx0 : (j == 1 ? hx1 : false);
+        halo = need && lane < 4;
+        halo_at = j * SL + dist * CW + halo_slot;
+        if (halo) hv = src[(size_t)(2 * (i0 + j) + dist) * N + own + halo_src];
     };
     FdCell<D, P, C0, C1> c;
     c.load(rec, N, cell, ph);
-    issue(std::integral_constant<int, C0>{});
-    static_for<C0, C1>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        constexpr Vel v = V.v[i];
-        constexpr bool my = v.y != 0;
-        constexpr int sy = v.y > 0 ? 1 : -1, sz = v.z > 0 ? 1 : -1;
-        if constexpr (i != C0) __syncthreads();  // the previous population's reads are done
+    constexpr int kPhases = (C1 - C0 + PB - 1) / PB;
+    issue(std::integral_constant<int, 0>{});
+    static_for<0, kPhases>([&](auto Ph) {
+        constexpr int phz = decltype(Ph)::value;
+        constexpr int i0 = C0 + PB * phz;
+        constexpr int np = (C1 - i0) < PB ? (C1 - i0) : PB;
+        if constexpr (phz != 0) __syncthreads();  // the previous phase's reads are done
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < kMaxSets; ++m)
             if (has[m]) *reinterpret_cast<S4*>(lds + slot[m] + 4 * lane) = q[m];
-        if (halo) lds[wave * CW + halo_slot] = hv;
+        if (halo) lds[halo_at] = hv;
         __syncthreads();
-        if constexpr (i + 1 < C1) issue(std::integral_constant<int, i + 1>{});
-        auto at = [&](auto Dist, auto Ax, auto Dd) {
-            constexpr int dist = decltype(Dist)::value;
-            constexpr int ax = decltype(Ax)::value;
-            constexpr int d = decltype(Dd)::value;
-            if constexpr (d == 0 || ax == 0) {
-                return lds[dist * CW + 4 + tid + d];
-            } else {
-                constexpr int s = ax == 1 ? sy : sz;
-                constexpr int k = d == -2 * s ? 0 : (d == -s ? 1 : 2);
-                constexpr int blk = (ax == 2 && my) ? 2 : 0;  // y's rows come first
-                return lds[2 * CW + (3 * (blk + dist) + k) * 256 + tid];
-            }
-        };
-        c.template update<i>(ph, at, dst, N, cell);
+        if constexpr (phz + 1 < kPhases) issue(std::integral_constant<int, phz + 1>{});
+        static_for<0, np>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            constexpr int i = i0 + j;
+            constexpr Vel v = V.v[i];
+            constexpr bool my = v.y != 0;
+            constexpr int sy = v.y > 0 ? 1 : -1, sz = v.z > 0 ? 1 : -1;
+            const S* base = lds + j * SL;
+            auto at = [&](auto Dist, auto Ax, auto Dd) {
+                constexpr int dist = decltype(Dist)::value;
+                constexpr int ax = decltype(Ax)::value;
+                constexpr int d = decltype(Dd)::value;
+                if constexpr (d == 0 || ax == 0) {
+                    return base[dist * CW + 4 + tid + d];
+                } else {
+                    constexpr int s = ax == 1 ? sy : sz;
+                    constexpr int k = d == -2 * s ? 0 : (d == -s ? 1 : 2);
+                    constexpr int blk = (ax == 2 && my) ? 2 : 0;  // y's rows come first
+                    return base[2 * CW + (3 * (blk + dist) + k) * 256 + tid];
+                }
+            };
+            c.template update<i>(ph, at, dst, N, cell);
+        });
     });
     c.finish(rec, N, cell, ph);
 }
@@ -558,11 +594,12 @@ hipError_t launch_chunks(const StepArgs& a, typename P::T* rec, int grid, hipStr
         // rows of whole tiles: the LDS-staged kernel (its 16-byte row loads
         // need every row to start on a tile boundary)
         constexpr int c0 = chunk_begin<D>(C), c1 = chunk_end<D>(C);
-        hipError_t e = a.nx % 256 == 0
-                           ? launch_kernel(&k_fd_update_lds<D, P, c0, c1>, dim3(grid), dim3(256),
-                                           s, a.src, a.dst, rec, a)
-                           : launch_kernel(&k_fd_update<D, P, c0, c1>, dim3(grid), dim3(256), s,
-                                           a.src, a.dst, rec, a);
+        hipError_t e =
+            a.nx % 256 == 0
+                ? launch_kernel(&k_fd_update_lds<D, P, c0, c1, kFdPhase<D, P>>, dim3(grid),
+                                dim3(256), s, a.src, a.dst, rec, a)
+                : launch_kernel(&k_fd_update<D, P, c0, c1>, dim3(grid), dim3(256), s, a.src,
+                                a.dst, rec, a);
         if (e != hipSuccess) return e;
         return launch_chunks<D, P, C + 1>(a, rec, grid, s);
     }
