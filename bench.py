@@ -216,7 +216,7 @@ def cpu_baseline(p, seconds_hint=15.0):
     is reported alongside."""
     import numpy as np
 
-    from oracle.model import OracleLBM, num_threads
+    from oracle.model import OracleLBM, num_threads, set_num_threads
     from paper_1608_06345_amd import lbm
     from paper_1608_06345_amd.inputs import smooth_fields
 
@@ -242,6 +242,20 @@ def cpu_baseline(p, seconds_hint=15.0):
     err = {"rho": float(np.max(np.abs(r - r_o) / r_o)),
            "u": float(np.max(np.abs(u - u_o)) / np.max(np.abs(u_o))),
            "T": float(np.max(np.abs(T - T_o) / T_o))}
+    # the same recipe on one core, on a smaller sample
+    n1, steps1 = 32, 30
+    shape1 = (n1, n1, n1) if dim == 3 else (4 * n1, 4 * n1, 1)
+    o1 = OracleLBM(dim, p["gamma"], p["tf"], p["tg"], *shape1)
+    o1.init_fields(*smooth_fields(dim, *shape1, seed=p["seed"]))
+    threads = num_threads()
+    set_num_threads(1)
+    try:
+        t1 = time.perf_counter()
+        o1.step(steps1)
+        dt1 = time.perf_counter() - t1
+    finally:
+        set_num_threads(threads)
+    cells1 = shape1[0] * shape1[1] * shape1[2]
     cpu_model = ""
     try:
         with open("/proc/cpuinfo") as fh:
@@ -256,7 +270,11 @@ def cpu_baseline(p, seconds_hint=15.0):
             "sample": f"FP64 oracle, D{dim}Q{o.Q} "
                       f"{'x'.join(str(v) for v in shape[:dim])} periodic, same recipe and "
                       f"parameters as the headline, {steps} steps ({dt:.1f} s)",
-            "cpu_model": cpu_model, "gpu_vs_oracle_max_rel_err": err}
+            "cpu_model": cpu_model, "gpu_vs_oracle_max_rel_err": err,
+            "single_core": {"value": round(cells1 * steps1 / dt1 / 1e6, 3), "unit": "MLUPS",
+                            "cores": 1,
+                            "sample": f"same recipe, {'x'.join(str(v) for v in shape1[:dim])}, "
+                                      f"{steps1} steps ({dt1:.1f} s)"}}
 
 
 def main():
