@@ -1,0 +1,36 @@
+"""Host-side checks of bench.py (no GPU): the one-GPU guard, the algorithmic
+byte counts its roofline divides by, and the workloads it times."""
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_algorithmic_bytes_per_cell_update():
+    # one read and one write of each of the 2Q stored values (g and h)
+    for dim, q in ((2, 37), (3, 107)):
+        for store, size in (("fp64", 8), ("fp32", 4), ("fp16", 2)):
+            assert bench.bytes_per_update(dim, store) == 2 * q * 2 * size
+    assert bench.bytes_per_update(3, "fp32") == 1712
+    assert bench.bytes_per_update(2, "fp64") == 1184
+
+
+def test_headline_and_paths():
+    p = bench.PATHS["d3q107_fp32"]
+    assert p["dim"] == 3 and p["shape"] == (256, 256, 256) and p["store"] == "fp32"
+    assert "D3Q107 256x256x256" in bench.describe("d3q107_fp32", p)
+    for name, p in bench.PATHS.items():
+        d = bench.describe(name, p)
+        assert ("finite-difference" in d) == ("dt" in p)
+        assert ("LDS" in d) == (p.get("variant") == "split_lds")
+    assert len(bench.kernel_source_hash()) == 16
