@@ -132,8 +132,8 @@ int create_solver(int dim, int velocity_set, double gamma, double tau_f, double 
 // neighbour rows still fit the L2 and it streams faster than the two-pass
 // step with its one-lane update kernel (measured on 4096^2: 5.9 ms fused,
 // 8.7 ms two-pass with that kernel); with the LDS-staged update the
-// two-pass step is faster (5.4 ms).  D3Q107 FP32 256^3: 31.7 ms fused,
-// 10.3 ms two-pass.
+// two-pass step is faster (5.4-5.6 ms).  D3Q107 FP32 256^3: 31.7 ms fused,
+// 10.2 ms two-pass.
 bool fd_fused_by_default(int dim, int precision, int64_t nx) {
     return dim == 2 && precision == LBM_FP64 && nx % 256 != 0;
 }

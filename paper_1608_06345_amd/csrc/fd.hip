@@ -161,7 +161,6 @@ __global__ __launch_bounds__(256) void k_fd_moments(const void* __restrict__ src
                                                     const Physics ph) {
     using T = typename P::T;
     using S = typename P::S;
-    constexpr bool DEV = P::kDev;
     constexpr VelSet<D> V = kVelSet<D>;
     constexpr int Q = VelSet<D>::Q;
     const int64_t cell = (int64_t)blockIdx.x * 256 + threadIdx.x;

@@ -19,6 +19,8 @@
 //   4. relax  g_i' = g_i + (F_i - g_i)/tau_f,
 //             h_i' = h_i + ((delta/2) T F_i - h_i)/tau_g;
 //   5. store  g_i', h_i' at x (coalesced).
+// The D3Q107 step also comes with its pulled rows staged in LDS
+// (k_step_split_lds, variant SPLIT_LDS): same results, measured slower.
 #include <tuple>
 #include <type_traits>
 #include <utility>
@@ -120,7 +122,7 @@ void k_step_split(const StepArgs a) {
 // rows of whole 128-cell tiles).  A workgroup serves one 128-cell tile of a
 // row, its four waves 32 cells each as in k_step_split.  The pull of
 // population i reads the tile's row shifted by e_i: row (y - e_y, z - e_z),
-// cells x0 - e_x ..  x0 - e_x + 127.  Instead of one 4-byte (or 2-byte) load
+// cells x0 - e_x .. x0 - e_x + 127.  Instead of one 4-byte (or 2-byte) load
 // per lane and population, the workgroup loads that row once with 4-cell
 // loads per lane -- lanes 0..31 the g row, lanes 32..63 the h row, one
 // instruction per population -- plus up to three halo cells either side,
