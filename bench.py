@@ -15,7 +15,16 @@ stream the kernels run on.
 
 Roofline: algorithmic bytes per cell update = 2 (read + write) x Q x 2
 (g and h) x bytes per stored value (8, 4 or 2); achieved GB/s = those bytes x cells / average
-launch time; peak = 8 TB/s HBM3E.
+launch time; peak = 8 TB/s HBM3E.  Beside the peak, the same run measures
+what plain data movement reaches on this device: a streaming copy and a
+read-only sweep over as many bytes as one headline launch moves
+(libhbmprobe.so).
+
+The oracle leg (cpu_baseline, skipped with --no-cpu) times the FP64 CPU
+oracle on a bounded sample of the headline workload, and puts the GPU's error
+against the oracle next to every path, on a small sample of that path's own
+recipe; for the shock-tube ensemble it adds each tube's L1 error against the
+exact Riemann solution.
 """
 import argparse
 import hashlib
@@ -41,6 +50,9 @@ for _store in ("fp32", "fp64", "fp16"):
 for _store in ("fp32", "fp64", "fp16"):
     PATHS[f"d2q37_{_store}"] = dict(dim=2, shape=(4096, 4096, 1), gamma=1.4, tf=0.7, tg=0.8,
                                     store=_store, seed=2, steps=1000)
+# gamma = 5/3 in 3D: delta = 0, so h carries nothing; it is still stored,
+# loaded, relaxed and written in full (no h-skipping specialisation).
+PATHS["d3q107_fp32_gamma53"] = dict(PATHS["d3q107_fp32"], gamma=5.0 / 3.0, steps=200)
 # The D3Q107 step with its pulled rows staged in LDS (variant SPLIT_LDS),
 # beside the default kernel that pulls straight from global memory.
 for _store in ("fp32", "fp64", "fp16"):
@@ -73,11 +85,12 @@ def describe(name, p):
     q = 37 if p["dim"] == 2 else 107
     grid = "x".join(str(n) for n in p["shape"][:p["dim"]])
     delta = 2.0 / (p["gamma"] - 1.0) - p["dim"]
+    delta = 0.0 if abs(delta) < 1e-9 else delta
     scheme = (f"finite-difference form, dt {p['dt']:.4f}, " if p.get("dt") else "")
     if p.get("variant") == "split_lds":
         scheme = "pulled rows staged in LDS, "
     return (f"D{p['dim']}Q{q} {grid} periodic, smooth seeded field (seed {p['seed']}), "
-            f"{scheme}gamma {p['gamma']} (delta {delta:g}), tau_f {p['tf']}, tau_g {p['tg']}, "
+            f"{scheme}gamma {p['gamma']:.6g} (delta {delta:g}), tau_f {p['tf']}, tau_g {p['tg']}, "
             f"{STORAGE[p['store']][0]}")
 
 
@@ -152,8 +165,65 @@ def run_path(name, p, steps, warmup):
     }
 
 
-def serving_runs(measured_gbs, n_requests, servers=("pool", "sequential"), ensemble=True,
-                 rate=None):
+def hbm_ceiling(nbytes, reps=5):
+    """What plain data movement reaches on this device (libhbmprobe.so): a
+    streaming copy of nbytes / 2 bytes (nbytes of HBM traffic) and a
+    read-only sweep of nbytes, each launch shape timed over `reps` launches
+    with HIP events on the stream they run on, after one untimed launch.
+    GB/s counts the bytes each launch must move (copy: read + write)."""
+    import ctypes
+
+    import torch
+
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1608_06345_amd", "libhbmprobe.so"))
+    vp, sz, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
+    lib.hbm_probe_variants.argtypes = [i32]
+    lib.hbm_probe_variant_name.argtypes = [i32, i32]
+    lib.hbm_probe_variant_name.restype = ctypes.c_char_p
+    lib.hbm_probe_copy.argtypes = [vp, vp, sz, i32, vp]
+    lib.hbm_probe_read.argtypes = [vp, sz, i32, vp, vp]
+    half = (nbytes // 2) // 4096 * 4096
+    buf = torch.empty(2 * half, dtype=torch.uint8, device="cuda")
+    buf.fill_(1)  # ordinary float data (every float reads 2.4e-38)
+    sink = torch.zeros(256, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.Stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    src, dst = buf.data_ptr(), buf.data_ptr() + half
+    out = {"copy": {}, "read": {}, "copy_bytes_per_launch": 2 * half,
+           "read_bytes_per_launch": 2 * half}
+    torch.cuda.synchronize()
+    for kind in (0, 1):
+        for v in range(lib.hbm_probe_variants(kind)):
+            name = lib.hbm_probe_variant_name(kind, v).decode()
+
+            def once():
+                if kind == 0:
+                    rc = lib.hbm_probe_copy(ctypes.c_void_p(dst), ctypes.c_void_p(src), half, v,
+                                            sp)
+                else:
+                    rc = lib.hbm_probe_read(ctypes.c_void_p(src), 2 * half, v,
+                                            ctypes.c_void_p(sink.data_ptr()), sp)
+                if rc != 0:
+                    raise RuntimeError(f"hbm probe kind {kind} variant {name}: status {rc}")
+
+            once()
+            start = torch.cuda.Event(enable_timing=True)
+            end = torch.cuda.Event(enable_timing=True)
+            start.record(stream)
+            for _ in range(reps):
+                once()
+            end.record(stream)
+            torch.cuda.synchronize()
+            ms = start.elapsed_time(end) / reps
+            out["copy" if kind == 0 else "read"][name] = round(2 * half / (ms * 1e-3) / 1e9, 1)
+    del buf, sink
+    torch.cuda.empty_cache()
+    out["copy_gbs"] = max(out["copy"].values())
+    out["read_gbs"] = max(out["read"].values())
+    return out
+
+
+def serving_runs(n_requests, servers=("pool", "sequential"), ensemble=True, rate=None):
     """The batched serving form.
 
     tube_ensemble: 512 quasi-1D shock tubes (D2Q37, Nx log-uniform in
@@ -163,9 +233,12 @@ def serving_runs(measured_gbs, n_requests, servers=("pool", "sequential"), ensem
       one captured 1000-step graph.
     poisson_trace: the mixed request stream (50% 2D 256^2..2048^2, 30% 3D
       64^3..192^3, 20% tubes; gamma in [1.1, 1.67]; 200..2000 steps) arriving
-      at 80% of the batched capacity estimated from the bandwidth just
-      measured, served (a) by continuous batching in an FP32 pool with 8-step
-      graph replays and (b) one request at a time in FP64 with eager launches.
+      at 80% of the pool's measured capacity on this mix, served (a) by
+      continuous batching in an FP32 pool with 8-step graph replays and (b)
+      one request at a time in FP64 with eager launches.  Capacity: the cell
+      updates per second the pool sustained over a back-to-back run of the
+      trace's first 48 requests (all taken as arrived at once), divided by
+      the mean cell updates per request of the mix.
     """
     import torch
 
@@ -182,15 +255,28 @@ def serving_runs(measured_gbs, n_requests, servers=("pool", "sequential"), ensem
         torch.cuda.empty_cache()
         print(f"# tube ensemble: {out['tube_ensemble']}", file=sys.stderr, flush=True)
 
+    budget = int(250e9)  # the admission cap of the serving configuration
+    pt = {"requests": n_requests}
     if rate is None:
-        probe = serving.poisson_trace(400, 1.0, seed=5)
-        mean_bytes = np.mean([serving.request_bytes_moved(r) for r in probe if serving.valid(r)])
-        rate = 0.8 * measured_gbs * 1e9 / mean_bytes
+        mix = serving.poisson_trace(400, 1.0, seed=5)
+        mean_updates = np.mean([r.cells * r.req.steps for r in mix
+                                if lbm.lbm_pool_request_bytes(r.req, lbm.LBM_FP32_DEV) > 0])
+        cal = serving.poisson_trace(48, 1.0, seed=5)
+        tr, span = serving.serve_pool(cal, budget, max_slots=256, ticks=8, realtime=False)
+        cal_sum = serving.summarize(tr, span)
+        capacity = cal_sum["aggregate_mlups_all_admitted"] * 1e6 / mean_updates
+        rate = 0.8 * capacity
+        pt["capacity"] = {"requests_per_s": round(capacity, 3),
+                          "pool_mlups_back_to_back": cal_sum["aggregate_mlups_all_admitted"],
+                          "mean_cell_updates_per_request": float(mean_updates),
+                          "calibration_requests": 48, "makespan_s": cal_sum["makespan_s"]}
+        torch.cuda.empty_cache()
+        print(f"# serving capacity on the mix: {pt['capacity']}", file=sys.stderr, flush=True)
     every = 50 if n_requests >= 200 else 0
-    pt = {"rate_per_s": round(rate, 3), "requests": n_requests}
+    pt["rate_per_s"] = round(rate, 3)
     if "pool" in servers:
         trace = serving.poisson_trace(n_requests, rate, seed=5)
-        tr, span = serving.serve_pool(trace, 250 << 30, max_slots=256, ticks=8,
+        tr, span = serving.serve_pool(trace, budget, max_slots=256, ticks=8,
                                       progress_every=every)
         pt["fp32_pool_continuous_batching"] = serving.summarize(tr, span)
         torch.cuda.empty_cache()
@@ -207,17 +293,58 @@ def serving_runs(measured_gbs, n_requests, servers=("pool", "sequential"), ensem
     return out
 
 
-def cpu_baseline(p, seconds_hint=15.0):
-    """The FP64 oracle, as it stands, on a bounded sample of the headline
-    workload: the same lattice, parameters and field recipe on a 64^3 grid
-    (256^3 would take over a minute per step on the host), timed over a
-    fixed number of steps.  MLUPS is per cell update, so it needs no
-    rescaling.  The GPU runs the same sample; its deviation from the oracle
-    is reported alongside."""
-    import numpy as np
+def _errors(gpu, ref):
+    """rho and T pointwise relative; u relative to max|u_oracle|."""
+    (r, u, T), (r_o, u_o, T_o) = gpu, ref
+    return {"rho": float(np.max(np.abs(r - r_o) / r_o)),
+            "u": float(np.max(np.abs(u - u_o)) / np.max(np.abs(u_o))),
+            "T": float(np.max(np.abs(T - T_o) / T_o)),
+            "max_abs_u_oracle": float(np.max(np.abs(u_o)))}
 
-    from oracle.model import OracleLBM, num_threads, set_num_threads
+
+def _gpu_sample(p, shape, steps, store=None, fields=None):
     from paper_1608_06345_amd import lbm
+    from paper_1608_06345_amd.inputs import smooth_fields
+
+    f = fields if fields is not None else smooth_fields(p["dim"], *shape, seed=p["seed"])
+    with lbm.Solver(p["dim"], p["gamma"], p["tf"], p["tg"], *shape,
+                    precision=precision_of(store or p["store"]), dt=p.get("dt")) as s:
+        if p.get("variant") == "split_lds":
+            s.set_variant(lbm.LBM_VARIANT_SPLIT_LDS)
+        s.init_fields(*f)
+        s.step(steps)
+        rho, u, _ = s.moments()
+        T = s.temperature()
+    return rho, u, T
+
+
+# Same-recipe samples for the per-path error against the oracle: small
+# enough for the host, rows a multiple of 256 cells (the LDS kernels' tile).
+ACCURACY_SAMPLES = {
+    ("lattice", 3): ((256, 24, 24), 80),
+    ("lattice", 2): ((256, 256, 1), 300),
+    ("fd", 3): ((256, 16, 16), 100),
+    ("fd", 2): ((256, 128, 1), 300),
+}
+
+
+def cpu_baseline(p, paths, tubes=False):
+    """The oracle leg.
+
+    1. Timing: the FP64 oracle, as it stands, on a bounded sample of the
+       headline workload -- the same lattice, parameters and field recipe on
+       a 64^3 grid (256^3 would take over a minute per step on the host),
+       over a fixed number of steps, on all host threads and (a smaller
+       sample) on one.  MLUPS is per cell update, so it needs no rescaling.
+       The GPU runs the same sample and its error is reported beside it.
+    2. Accuracy of every path in `paths` (adds "max_rel_err_vs_oracle" to
+       each): the path's own recipe, parameters, storage and kernel variant
+       on a small grid (ACCURACY_SAMPLES), against the oracle run once per
+       distinct recipe.
+    3. With `tubes`, the shock-tube ensemble against the exact Riemann
+       solution (tube_accuracy), returned under "tube_accuracy".
+    """
+    from oracle.model import OracleLBM, num_threads, set_num_threads
     from paper_1608_06345_amd.inputs import smooth_fields
 
     n = 64
@@ -232,16 +359,8 @@ def cpu_baseline(p, seconds_hint=15.0):
     dt = time.perf_counter() - t0
     cells = shape[0] * shape[1] * shape[2]
     r_o, u_o, E_o = o.moments()
-    T_o = o.temperature(u_o, E_o)
-    prec = precision_of(p["store"])
-    with lbm.Solver(dim, p["gamma"], p["tf"], p["tg"], *shape, precision=prec) as s:
-        s.init_fields(*f)
-        s.step(steps)
-        r, u, E = s.moments()
-        T = s.temperature(u, E)
-    err = {"rho": float(np.max(np.abs(r - r_o) / r_o)),
-           "u": float(np.max(np.abs(u - u_o)) / np.max(np.abs(u_o))),
-           "T": float(np.max(np.abs(T - T_o) / T_o))}
+    ref = (r_o, u_o, o.temperature(u_o, E_o))
+    err = _errors(_gpu_sample(p, shape, steps, fields=f), ref)
     # the same recipe on one core, on a smaller sample
     n1, steps1 = 32, 30
     shape1 = (n1, n1, n1) if dim == 3 else (4 * n1, 4 * n1, 1)
@@ -265,7 +384,27 @@ def cpu_baseline(p, seconds_hint=15.0):
                     break
     except OSError:
         pass
-    return {"value": round(cells * steps / dt / 1e6, 3), "unit": "MLUPS",
+
+    # per-path accuracy, one oracle run per distinct recipe
+    refs = {}
+    for name, path in paths.items():
+        q = PATHS[name]
+        key = ("fd" if q.get("dt") else "lattice", q["dim"])
+        shp, nst = ACCURACY_SAMPLES[key]
+        rk = (key, q["gamma"], q["tf"], q["tg"], q.get("dt"), q["seed"])
+        if rk not in refs:
+            fr = smooth_fields(q["dim"], *shp, seed=q["seed"])
+            orc = OracleLBM(q["dim"], q["gamma"], q["tf"], q["tg"], *shp, dt=q.get("dt"))
+            orc.init_fields(*fr)
+            orc.step(nst)
+            ro, uo, Eo = orc.moments()
+            refs[rk] = (fr, (ro, uo, orc.temperature(uo, Eo)))
+        fr, ref_p = refs[rk]
+        e = _errors(_gpu_sample(q, shp, nst, fields=fr), ref_p)
+        e["sample"] = f"{'x'.join(str(v) for v in shp[:q['dim']])}, {nst} steps, same recipe"
+        path["max_rel_err_vs_oracle"] = e
+    out = {"tube_accuracy": tube_accuracy()} if tubes else {}
+    return {**out, "value": round(cells * steps / dt / 1e6, 3), "unit": "MLUPS",
             "cores": num_threads(), "kind": "oracle",
             "sample": f"FP64 oracle, D{dim}Q{o.Q} "
                       f"{'x'.join(str(v) for v in shape[:dim])} periodic, same recipe and "
@@ -275,6 +414,77 @@ def cpu_baseline(p, seconds_hint=15.0):
                             "cores": 1,
                             "sample": f"same recipe, {'x'.join(str(v) for v in shape1[:dim])}, "
                                       f"{steps1} steps ({dt1:.1f} s)"}}
+
+
+def tube_accuracy(n=512, seed=4):
+    """Part of the oracle leg: every tube of the ensemble recipe against the
+    exact Riemann solution (Sec. V's reference) at its comparison step --
+    the last step at which every wave of the exact solution is still 10
+    cells from an end, at most 1000 -- run in one FP32 pool.  A tube is
+    "in range" when every state of its exact solution has 0.7 <= T <= 1.4
+    and Mach < 0.8 and no wave outruns the lattice (speed < 3r).  L1 per field
+    is relative to the size of that field's jump (rho, p) or to |u*|."""
+    import math
+
+    import torch
+
+    from oracle.riemann import RiemannSolution, l1_errors, shock_tube_profile
+    from paper_1608_06345_amd import lbm, serving
+
+    rr = lbm.lbm_lattice(37)[2]
+    tubes = serving.tube_ensemble(n, steps=1000, seed=seed)
+    meta = {}
+    for r in tubes:
+        left, right = r.tube
+        g = r.req.gamma
+        sol = RiemannSolution(left, right, g)
+        nx = r.req.nx
+        x_d = nx // 2
+        n_cmp = max(1, min(1000, int((min(x_d, nx - x_d) - 10) * rr / sol.max_speed())))
+        states = [left, right, (sol.rho_star_l, sol.u_star, sol.p_star),
+                  (sol.rho_star_r, sol.u_star, sol.p_star)]
+        temps = [pp / rho for rho, _, pp in states]
+        mach = max(abs(u) / math.sqrt(g * pp / rho) for rho, u, pp in states)
+        in_range = (min(temps) >= 0.7 and max(temps) <= 1.4 and mach < 0.8
+                    and sol.max_speed() < 3 * rr)
+        r.req.steps = n_cmp
+        meta[r.rid] = (sol, n_cmp, in_range)
+    got = {}
+
+    def keep(r, pool, slot):
+        rho, u, _ = pool.moments(slot)
+        got[r.rid] = (rho, u, pool.temperature(slot))
+
+    budget = sum(lbm.lbm_pool_request_bytes(r.req, lbm.LBM_FP32_DEV) for r in tubes) + (1 << 30)
+    serving.serve_pool(tubes, budget, max_slots=600, ticks=50, realtime=False, keep=keep)
+    torch.cuda.empty_cache()
+    rel_in, rel_all, bad = [], [], 0
+    for r in tubes:
+        sol, n_cmp, in_range = meta[r.rid]
+        rho, u, T = got[r.rid]
+        nx = r.req.nx
+        if not np.all(np.isfinite(rho[:nx])):
+            bad += 1
+            continue
+        ex = shock_tube_profile(r.tube[0], r.tube[1], r.req.gamma, nx, n_cmp, rr)
+        l1 = l1_errors(rho[:nx], u[0][:nx], (rho * T)[:nx], *ex)
+        scale = (abs(r.tube[0][0] - r.tube[1][0]), max(1e-3, abs(sol.u_star)),
+                 abs(r.tube[0][2] - r.tube[1][2]))
+        rel = max(a / sc for a, sc in zip(l1, scale))
+        rel_all.append(rel)
+        if in_range:
+            rel_in.append(rel)
+
+    def stats(v):
+        return ({"median": round(float(np.median(v)), 5), "max": round(float(np.max(v)), 5)}
+                if v else None)
+
+    return {"tubes": n, "in_range": sum(1 for m in meta.values() if m[2]),
+            "non_finite_at_comparison_step": bad,
+            "relative_l1_in_range": stats(rel_in), "relative_l1_all_finite": stats(rel_all),
+            "normalisation": "each tube's temperatures scaled to geometric mean 1",
+            "tau": 0.8, "storage": "FP32 deviation storage",
+            "comparison_step": "last step with every exact wave 10 cells from an end (<= 1000)"}
 
 
 def main():
@@ -294,7 +504,9 @@ def main():
                          "these servers (no other paths, no tube ensemble, no CPU baseline)")
     ap.add_argument("--serving-rate", type=float, default=None,
                     help="arrival rate of the serving trace in requests/s (default: 80%% of "
-                         "the capacity estimated from the headline bandwidth)")
+                         "the pool's capacity measured on the same mix)")
+    ap.add_argument("--no-ceiling", action="store_true",
+                    help="skip the HBM copy / read ceiling probe")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy a device buffer of BYTES bytes 5 times (a plain copy "
                          "kernel of known size, to scale the HBM byte counters) and exit")
@@ -330,6 +542,12 @@ def main():
             print(f"# {name}: {paths[name]['mlups']} MLUPS, {paths[name]['gbs']} GB/s",
                   file=sys.stderr, flush=True)
     traffic = res["traffic_bytes_per_launch"]
+    algo_bytes = res["bytes_per_update"] * res["cells"]
+    ceiling = None
+    if not args.no_ceiling and not args.serving_only:
+        ceiling = hbm_ceiling(algo_bytes)
+        print(f"# HBM ceiling: copy {ceiling['copy_gbs']} GB/s, read {ceiling['read_gbs']} GB/s",
+              file=sys.stderr, flush=True)
     out = {
         "metric": "MLUPS (million lattice-cell updates per second)",
         "value": res["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
@@ -348,21 +566,32 @@ def main():
                      "traffic": (round(traffic / (res["ms_per_step"] * 1e-3) / 1e9, 1)
                                  if traffic else None),
                      "traffic_bytes_per_launch": traffic,
-                     "algorithmic_bytes_per_launch": res["bytes_per_update"] * res["cells"],
+                     "algorithmic_bytes_per_launch": algo_bytes,
                      "bytes_per_update": res["bytes_per_update"],
                      "kernel": "k_step_split (fused pull, moments, equilibrium, relax, store)"},
         "paths": {k: {kk: v[kk] for kk in ("workload", "mlups", "gbs", "hbm_frac",
                                             "ms_per_step", "steps")}
                   for k, v in paths.items()},
     }
+    if ceiling:
+        # measured in this run, on this device, over as many bytes as one
+        # headline launch moves
+        out["roofline"].update({
+            "copy_gbs": ceiling["copy_gbs"], "read_gbs": ceiling["read_gbs"],
+            "frac_of_copy": round(res["gbs"] / ceiling["copy_gbs"], 4),
+            "ceiling_probe": ceiling})
     if args.serving_only:
         servers = ("pool", "sequential") if args.serving_only == "both" else (args.serving_only,)
-        out["serving"] = serving_runs(res["gbs"], args.serving_requests, servers=servers,
-                                      ensemble=False, rate=args.serving_rate)
+        out["serving"] = serving_runs(args.serving_requests, servers=servers, ensemble=False,
+                                      rate=args.serving_rate)
     elif not args.no_serving:
-        out["serving"] = serving_runs(res["gbs"], args.serving_requests, rate=args.serving_rate)
+        out["serving"] = serving_runs(args.serving_requests, rate=args.serving_rate)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(head)
+        ens = out.get("serving", {}).get("tube_ensemble")
+        out["cpu_baseline"] = cpu_baseline(head, out["paths"], tubes=ens is not None)
+        if ens is not None:
+            ens["accuracy_vs_exact_riemann"] = out["cpu_baseline"].pop("tube_accuracy")
+        print("# oracle leg done", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 

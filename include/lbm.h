@@ -203,21 +203,33 @@ int lbm_init_fields(lbm_handle h, const double *rho, const double *u,
 int lbm_init_fields_dev(lbm_handle h, const double *rho, const double *u,
                         const double *T);
 
-/* Advance n >= 0 steps, asynchronously on the handle's stream: collide, then
- * stream every population e_i cells (lattice streaming), or n explicit
- * finite-difference steps of size dt (lbm_create_fd).  ESTATE before init;
- * EINVAL for n < 0. */
+/* Advance n >= 0 steps, asynchronously on the handle's stream.  One step of
+ * lattice streaming is S_{n+1} = Stream(Collide(S_n)): the BGK collision of
+ * both reduced distributions toward their Sec. IV equilibria (the relaxation
+ * of the Sec. II BGK equations, discretised explicitly in time as in
+ * Sec. III), then every population moves e_i cells, the lattice time step
+ * implied by Sec. V's time conversion t = step / (X r).  With lbm_create_fd
+ * a step is instead one explicit finite-difference step of size dt
+ * (Sec. III).  ESTATE before init; EINVAL for n < 0. */
 int lbm_step(lbm_handle h, int64_t n);
 
 /* Moments of S_n (Sec. II): rho [ncells], u [dim][ncells] and the specific
  * total energy E = (sum xi^2 g / 2 + sum h) / rho [ncells], in FP64 host
- * arrays; synchronous.  The temperature follows as
- * T = (2E - |u|^2) / (dim + delta).  ESTATE before init. */
+ * arrays; synchronous.  ESTATE before init. */
 int lbm_moments(lbm_handle h, double *rho, double *u, double *E);
 /* Same into device arrays, asynchronous on the handle's stream. */
 int lbm_moments_dev(lbm_handle h, double *rho, double *u, double *E);
 
-/* Domain totals of S_n in FP64: mass = sum rho, mom[k] = sum rho u_k
+/* Temperature of S_n (Sec. II: E = |u|^2/2 + (D + delta) T / 2, so
+ * T = (2E - |u|^2) / (D + delta)), formed per cell in FP64 on the device from
+ * the same moment sums lbm_moments reports.  T [ncells] FP64 host array;
+ * synchronous.  ESTATE before init; EINVAL on a NULL pointer. */
+int lbm_temperature(lbm_handle h, double *T);
+/* Same into a device array, asynchronous on the handle's stream. */
+int lbm_temperature_dev(lbm_handle h, double *T);
+
+/* Domain totals of S_n in FP64, from the Sec. II moments summed over every
+ * cell: mass = sum rho, mom[k] = sum rho u_k
  * (mom has dim entries), energy = sum rho E; deterministic summation order.
  * Synchronous.  ESTATE before init; ENONFINITE (totals still written) if any
  * total is NaN or infinite. */
@@ -295,8 +307,9 @@ int lbm_pool_destroy(lbm_pool_handle p);
 int lbm_pool_set_stream(lbm_pool_handle p, void *stream);
 
 /* Arena bytes a request occupies (both distributions, both ping-pong
- * sides); 0 if the request's shape is invalid.  This is the admission
- * footprint. */
+ * sides); 0 if the request is invalid in any respect lbm_pool_admit rejects
+ * with EINVAL (shape, gamma giving delta < 0, rates, steps, bc).  This is the
+ * admission footprint. */
 size_t lbm_pool_request_bytes(const lbm_request *r, int precision);
 
 /* Admit a request with its initial fields (as lbm_init_fields: host
@@ -334,6 +347,8 @@ int lbm_pool_moments_dev(lbm_pool_handle p, int slot, double *rho, double *u,
                          double *E);
 int lbm_pool_totals(lbm_pool_handle p, int slot, double *mass, double *mom,
                     double *energy);
+/* Temperature of a slot's S_n, as lbm_temperature (Sec. II). */
+int lbm_pool_temperature(lbm_pool_handle p, int slot, double *T);
 
 /* Free a slot and its arena space (synchronises the pool's stream first). */
 int lbm_pool_release(lbm_pool_handle p, int slot);

@@ -91,7 +91,7 @@ lbm::StepArgs step_args(const lbm_solver* h, const void* src, void* dst, bool st
 }
 
 // Readout of S_n into the given device outputs (any may be null).
-int readout(lbm_solver* h, double* rho, double* u, double* E, bool totals) {
+int readout(lbm_solver* h, double* rho, double* u, double* E, double* T, bool totals) {
     lbm::ReadArgs a;
     std::memset(&a, 0, sizeof(a));
     // Lattice scheme: S_0 sits unstreamed in the idle side; later
@@ -111,10 +111,12 @@ int readout(lbm_solver* h, double* rho, double* u, double* E, bool totals) {
     a.open_end = (h->bc & 3u) | (((h->bc >> 2) & 3u) << 1) | (((h->bc >> 4) & 3u) << 2);
     a.r = h->lat->r;
     a.rest_energy = 0.5 * (h->dim + h->delta);
+    a.inv_dof = 1.0 / (h->dim + h->delta);
     for (int g = 0; g < h->lat->groups; ++g) a.w[g] = h->lat->w_group[g];
     a.rho = rho;
     a.u = u;
     a.E = E;
+    a.T = T;
     a.partials = totals ? h->partials : nullptr;
     LBM_HIP(lbm::launch_readout(h->dim, h->precision, a, h->read_blocks, h->stream));
     if (totals)
@@ -126,6 +128,15 @@ int readout(lbm_solver* h, double* rho, double* u, double* E, bool totals) {
 int create_solver(int dim, int velocity_set, double gamma, double tau_f, double tau_g, double dt,
                   int64_t nx, int64_t ny, int64_t nz, uint32_t bc, int precision,
                   lbm_handle* out);
+
+}  // namespace
+
+int lbm::solver_readout(lbm_solver* h, double* rho, double* u, double* E, double* T,
+                        bool totals) {
+    return readout(h, rho, u, E, T, totals);
+}
+
+namespace {
 
 // Finite differences, AUTO variant: the two-pass step, except for D2Q37 in
 // FP64 on rows that are not whole 256-cell tiles.  There the fused kernel's
@@ -420,7 +431,7 @@ int lbm_step(lbm_handle h, int64_t n) {
 int lbm_moments_dev(lbm_handle h, double* rho, double* u, double* E) {
     if (!h || !rho || !u || !E) return LBM_EINVAL;
     if (!h->have_state) return LBM_ESTATE;
-    return readout(h, rho, u, E, false);
+    return readout(h, rho, u, E, nullptr, false);
 }
 
 int lbm_moments(lbm_handle h, double* rho, double* u, double* E) {
@@ -429,7 +440,7 @@ int lbm_moments(lbm_handle h, double* rho, double* u, double* E) {
     const size_t n = (size_t)h->N * sizeof(double);
     double* d = nullptr;
     LBM_HIP(hipMalloc((void**)&d, n * (2 + h->dim)));
-    int rc = readout(h, d, d + 2 * h->N, d + h->N, false);
+    int rc = readout(h, d, d + 2 * h->N, d + h->N, nullptr, false);
     hipError_t e = hipSuccess;
     if (rc == LBM_OK) e = hipMemcpyAsync(rho, d, n, hipMemcpyDeviceToHost, h->stream);
     if (rc == LBM_OK && e == hipSuccess)
@@ -443,10 +454,32 @@ int lbm_moments(lbm_handle h, double* rho, double* u, double* E) {
     return dev_err(es);
 }
 
+int lbm_temperature_dev(lbm_handle h, double* T) {
+    if (!h || !T) return LBM_EINVAL;
+    if (!h->have_state) return LBM_ESTATE;
+    return readout(h, nullptr, nullptr, nullptr, T, false);
+}
+
+int lbm_temperature(lbm_handle h, double* T) {
+    if (!h || !T) return LBM_EINVAL;
+    if (!h->have_state) return LBM_ESTATE;
+    const size_t n = (size_t)h->N * sizeof(double);
+    double* d = nullptr;
+    LBM_HIP(hipMalloc((void**)&d, n));
+    int rc = readout(h, nullptr, nullptr, nullptr, d, false);
+    hipError_t e = hipSuccess;
+    if (rc == LBM_OK) e = hipMemcpyAsync(T, d, n, hipMemcpyDeviceToHost, h->stream);
+    const hipError_t es = hipStreamSynchronize(h->stream);
+    (void)hipFree(d);
+    if (rc != LBM_OK) return rc;
+    if (e != hipSuccess) return dev_err(e);
+    return dev_err(es);
+}
+
 int lbm_totals(lbm_handle h, double* mass, double* mom, double* energy) {
     if (!h || !mass || !mom || !energy) return LBM_EINVAL;
     if (!h->have_state) return LBM_ESTATE;
-    int rc = readout(h, nullptr, nullptr, nullptr, true);
+    int rc = readout(h, nullptr, nullptr, nullptr, nullptr, true);
     if (rc != LBM_OK) return rc;
     double t[8];
     LBM_HIP(hipMemcpyAsync(t, h->totals, (h->dim + 2) * sizeof(double), hipMemcpyDeviceToHost,

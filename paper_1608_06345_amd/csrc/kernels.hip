@@ -340,9 +340,9 @@ void k_fd_step(const StepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Readout of S_n in double: per-cell rho, u, E and/or per-workgroup partial
-// totals (rho, rho u, rho E), reduced across the wave and the workgroup in a
-// fixed order.
+// Readout of S_n in double (Sec. II moments): per-cell rho, u, E, T and/or
+// per-workgroup partial totals (rho, rho u, rho E), reduced across the wave
+// and the workgroup in a fixed order.
 template <int D, class P>
 __global__ __launch_bounds__(kReadBlock) void k_readout(const ReadArgs a) {
     constexpr VelSet<D> V = kVelSet<D>;
@@ -389,6 +389,13 @@ __global__ __launch_bounds__(kReadBlock) void k_readout(const ReadArgs a) {
             for (int k = 0; k < D; ++k) a.u[k * a.N + cell] = tot[1 + k] / rho;
         }
         if (a.E) a.E[cell] = rhoE / rho;
+        if (a.T) {
+            // Sec. II: E = |u|^2 / 2 + (D + delta) T / 2
+            double uu = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) uu += (tot[1 + k] / rho) * (tot[1 + k] / rho);
+            a.T[cell] = (2.0 * (rhoE / rho) - uu) * a.inv_dof;
+        }
     }
     if (!a.partials) return;
     // wave reduction (fixed butterfly), then across the 4 waves in order

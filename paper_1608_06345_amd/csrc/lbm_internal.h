@@ -80,10 +80,12 @@ struct ReadArgs {
     int32_t stream;           // 1: the source holds P_{n-1}; pull to get S_n
     double r;
     double rest_energy;       // (D + delta) / 2, added back in deviation storage
+    double inv_dof;           // 1 / (D + delta): T = (2E - |u|^2) / (D + delta)
     double w[10];             // group weights (scaled storage is divided by them)
     double* rho;              // [N] or null
     double* u;                // [D][N] or null
     double* E;                // [N] or null
+    double* T;                // [N] or null
     double* partials;         // [blocks][D + 2] or null
 };
 
@@ -131,6 +133,13 @@ hipError_t launch_final_reduce(int dim, const double* partials, int blocks,
                                double* out, hipStream_t s);
 constexpr int kReadBlock = 256;
 
+}  // namespace lbm
+
+struct lbm_solver;
+namespace lbm {
+// Readout of a solve's S_n into device outputs (any may be null), with the
+// FP64 totals into the solve's own buffer when `totals` (api.hip).
+int solver_readout(lbm_solver* h, double* rho, double* u, double* E, double* T, bool totals);
 }  // namespace lbm
 
 // The opaque handle.

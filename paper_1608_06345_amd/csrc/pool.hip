@@ -380,7 +380,8 @@ int ensure_partials(lbm_pool* p, int64_t N) {
 }
 
 // Readout of a slot's S_n (n = its steps done), like a single solve's.
-int pool_readout(lbm_pool* p, int slot, double* rho, double* u, double* E, bool totals) {
+int pool_readout(lbm_pool* p, int slot, double* rho, double* u, double* E, double* T,
+                 bool totals) {
     const Slot& sl = p->slots[slot];
     POOL_HIP(hipMemcpyAsync(p->h_steps + slot, p->d_steps + slot, sizeof(int64_t),
                             hipMemcpyDeviceToHost, p->stream));
@@ -401,11 +402,13 @@ int pool_readout(lbm_pool* p, int slot, double* rho, double* u, double* E, bool 
     a.open_end = e.open_end;
     a.r = lbm::lattice_tables(sl.dim).r;
     a.rest_energy = 0.5 * (sl.dim + sl.delta);
+    a.inv_dof = 1.0 / (sl.dim + sl.delta);
     for (int g = 0; g < lbm::lattice_tables(sl.dim).groups; ++g)
         a.w[g] = lbm::lattice_tables(sl.dim).w_group[g];
     a.rho = rho;
     a.u = u;
     a.E = E;
+    a.T = T;
     const int blocks = (int)((sl.N + lbm::kReadBlock - 1) / lbm::kReadBlock);
     if (totals) {
         int rc = ensure_partials(p, sl.N);
@@ -493,17 +496,39 @@ int lbm_pool_set_stream(lbm_pool_handle p, void* stream) {
     return LBM_OK;
 }
 
-size_t lbm_pool_request_bytes(const lbm_request* r, int precision) {
+// Every check of a request that admission makes before looking at the pool's
+// state: shape, gamma (delta = 2/(gamma - 1) - D of Sec. II, snapped to 0
+// within 1e-9, must not be negative), rates, step count and boundary codes.
+static bool request_valid(const lbm_request* r, int precision, double* delta_out) {
     if (!r || (precision != LBM_FP64 && precision != LBM_FP32_DEV &&
                precision != LBM_FP16_SCALED))
-        return 0;
-    if (r->dim != 2 && r->dim != 3) return 0;
-    if (r->nx < 1 || r->ny < 1 || r->nz < 1 || (r->dim == 2 && r->nz != 1)) return 0;
+        return false;
+    if (r->dim != 2 && r->dim != 3) return false;
+    if (r->nx < 1 || r->ny < 1 || r->nz < 1 || (r->dim == 2 && r->nz != 1)) return false;
     const double N = (double)r->nx * (double)r->ny * (double)r->nz;
     const size_t elem = precision == LBM_FP64 ? 8 : (precision == LBM_FP32_DEV ? 4 : 2);
-    if (N * (double)elem > 2147483647.0) return 0;
+    if (N * (double)elem > 2147483647.0) return false;
+    if (!(r->gamma > 1.0) || !std::isfinite(r->gamma)) return false;
+    double delta = 2.0 / (r->gamma - 1.0) - r->dim;
+    if (std::fabs(delta) < 1e-9) delta = 0.0;
+    if (delta < 0.0) return false;
+    if (!(r->tau_f > 0.5) || !(r->tau_g > 0.5) || !std::isfinite(r->tau_f) ||
+        !std::isfinite(r->tau_g))
+        return false;
+    if (r->steps < 0 || (r->bc & ~0x3Fu)) return false;
+    for (int k = 0; k < 3; ++k)
+        if (((r->bc >> (2 * k)) & 3u) > LBM_BC_ZERO_GRADIENT) return false;
+    if (r->dim == 2 && ((r->bc >> 4) & 3u) != LBM_BC_PERIODIC) return false;
+    if (delta_out) *delta_out = delta;
+    return true;
+}
+
+size_t lbm_pool_request_bytes(const lbm_request* r, int precision) {
+    if (!request_valid(r, precision, nullptr)) return 0;
+    const size_t N = (size_t)r->nx * (size_t)r->ny * (size_t)r->nz;
+    const size_t elem = precision == LBM_FP64 ? 8 : (precision == LBM_FP32_DEV ? 4 : 2);
     const int q = r->dim == 2 ? LBM_D2Q37 : LBM_D3Q107;
-    const size_t bytes = 2 * 2 * (size_t)q * (size_t)N * elem;
+    const size_t bytes = 2 * 2 * (size_t)q * N * elem;
     return (bytes + 255) & ~(size_t)255;
 }
 
@@ -511,19 +536,9 @@ static int pool_admit(lbm_pool_handle p, const lbm_request* r, const double* rho
                       const double* u, const double* T, bool device, int* slot_out) {
     if (!p || !r || !rho || !u || !T || !slot_out) return LBM_EINVAL;
     *slot_out = -1;
+    double delta = 0.0;
+    if (!request_valid(r, p->precision, &delta)) return LBM_EINVAL;
     const size_t bytes = lbm_pool_request_bytes(r, p->precision);
-    if (!bytes) return LBM_EINVAL;
-    double delta = 2.0 / (r->gamma - 1.0) - r->dim;
-    if (!(r->gamma > 1.0) || !std::isfinite(r->gamma)) return LBM_EINVAL;
-    if (std::fabs(delta) < 1e-9) delta = 0.0;
-    if (delta < 0.0) return LBM_EINVAL;
-    if (!(r->tau_f > 0.5) || !(r->tau_g > 0.5) || !std::isfinite(r->tau_f) ||
-        !std::isfinite(r->tau_g))
-        return LBM_EINVAL;
-    if (r->steps < 0 || (r->bc & ~0x3Fu)) return LBM_EINVAL;
-    for (int k = 0; k < 3; ++k)
-        if (((r->bc >> (2 * k)) & 3u) > LBM_BC_ZERO_GRADIENT) return LBM_EINVAL;
-    if (r->dim == 2 && ((r->bc >> 4) & 3u) != LBM_BC_PERIODIC) return LBM_EINVAL;
     if (bytes > p->budget) return LBM_ENOMEM;  // can never fit
     int slot = -1;
     for (int s = 0; s < p->max_slots; ++s)
@@ -759,7 +774,7 @@ int lbm_pool_moments(lbm_pool_handle p, int slot, double* rho, double* u, double
     const size_t n = (size_t)sl.N * sizeof(double);
     double* d = nullptr;
     POOL_HIP(hipMalloc((void**)&d, n * (2 + sl.dim)));
-    rc = pool_readout(p, slot, d, d + 2 * sl.N, d + sl.N, false);
+    rc = pool_readout(p, slot, d, d + 2 * sl.N, d + sl.N, nullptr, false);
     hipError_t e = hipSuccess;
     if (rc == LBM_OK) e = hipMemcpyAsync(rho, d, n, hipMemcpyDeviceToHost, p->stream);
     if (rc == LBM_OK && e == hipSuccess)
@@ -777,14 +792,31 @@ int lbm_pool_moments_dev(lbm_pool_handle p, int slot, double* rho, double* u, do
     int rc = check_slot(p, slot);
     if (rc != LBM_OK) return rc;
     if (!rho || !u || !E) return LBM_EINVAL;
-    return pool_readout(p, slot, rho, u, E, false);
+    return pool_readout(p, slot, rho, u, E, nullptr, false);
+}
+
+int lbm_pool_temperature(lbm_pool_handle p, int slot, double* T) {
+    int rc = check_slot(p, slot);
+    if (rc != LBM_OK) return rc;
+    if (!T) return LBM_EINVAL;
+    const size_t n = (size_t)p->slots[slot].N * sizeof(double);
+    double* d = nullptr;
+    POOL_HIP(hipMalloc((void**)&d, n));
+    rc = pool_readout(p, slot, nullptr, nullptr, nullptr, d, false);
+    hipError_t e = hipSuccess;
+    if (rc == LBM_OK) e = hipMemcpyAsync(T, d, n, hipMemcpyDeviceToHost, p->stream);
+    const hipError_t es = hipStreamSynchronize(p->stream);
+    (void)hipFree(d);
+    if (rc != LBM_OK) return rc;
+    if (e != hipSuccess) return lbm::err_of(e);
+    return lbm::err_of(es);
 }
 
 int lbm_pool_totals(lbm_pool_handle p, int slot, double* mass, double* mom, double* energy) {
     int rc = check_slot(p, slot);
     if (rc != LBM_OK) return rc;
     if (!mass || !mom || !energy) return LBM_EINVAL;
-    rc = pool_readout(p, slot, nullptr, nullptr, nullptr, true);
+    rc = pool_readout(p, slot, nullptr, nullptr, nullptr, nullptr, true);
     if (rc != LBM_OK) return rc;
     const int dim = p->slots[slot].dim;
     double t[8];

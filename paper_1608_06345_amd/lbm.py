@@ -94,6 +94,8 @@ def _load():
         "lbm_step": [vp, i64],
         "lbm_moments": [vp, dp, dp, dp],
         "lbm_moments_dev": [vp, vp, vp, vp],
+        "lbm_temperature": [vp, dp],
+        "lbm_temperature_dev": [vp, vp],
         "lbm_totals": [vp, dp, dp, dp],
         "lbm_get_info": [vp, ctypes.POINTER(_Info)],
         "lbm_lattice": [i32, ctypes.POINTER(ctypes.c_int8), dp, dp],
@@ -109,6 +111,7 @@ def _load():
         "lbm_pool_moments": [vp, i32, dp, dp, dp],
         "lbm_pool_moments_dev": [vp, i32, vp, vp, vp],
         "lbm_pool_totals": [vp, i32, dp, dp, dp],
+        "lbm_pool_temperature": [vp, i32, dp],
         "lbm_pool_release": [vp, i32],
         "lbm_pool_get_info": [vp, ctypes.POINTER(_PoolInfo)],
     }
@@ -264,6 +267,20 @@ def lbm_moments_dev(h, rho, u, E):
                                 _dev_ptr(E, n)), "lbm_moments_dev")
 
 
+def lbm_temperature(h):
+    """T [cells] of S_n as an FP64 numpy array (formed by the library)."""
+    inf = lbm_get_info(h)
+    T = np.empty(inf["nx"] * inf["ny"] * inf["nz"])
+    _check(_lib.lbm_temperature(h, _dp(T)), "lbm_temperature")
+    return T
+
+
+def lbm_temperature_dev(h, T):
+    inf = lbm_get_info(h)
+    _check(_lib.lbm_temperature_dev(h, _dev_ptr(T, inf["nx"] * inf["ny"] * inf["nz"])),
+           "lbm_temperature_dev")
+
+
 def lbm_totals(h):
     """(mass, momentum [dim], energy); NonFiniteError if any is NaN/Inf."""
     inf = lbm_get_info(h)
@@ -341,9 +358,8 @@ class Solver:
     def moments(self):
         return lbm_moments(self.h)
 
-    def temperature(self, u, E):
-        inf = self.info
-        return (2.0 * E - np.sum(np.asarray(u) ** 2, axis=0)) / (inf["dim"] + inf["delta"])
+    def temperature(self):
+        return lbm_temperature(self.h)
 
     def totals(self):
         return lbm_totals(self.h)
@@ -477,6 +493,12 @@ class Pool:
             raise NonFiniteError(rc, "lbm_pool_totals", out)
         _check(rc, "lbm_pool_totals")
         return out
+
+    def temperature(self, slot):
+        req = self.requests[slot]
+        T = np.empty(req.nx * req.ny * req.nz)
+        _check(_lib.lbm_pool_temperature(self.p, slot, _dp(T)), "lbm_pool_temperature")
+        return T
 
     def release(self, slot):
         _check(_lib.lbm_pool_release(self.p, slot), "lbm_pool_release")

@@ -116,12 +116,6 @@ def poisson_trace(n, rate, seed=5, tube_steps=None):
     return out
 
 
-def valid(r):
-    """gamma must leave delta >= 0 (gamma <= 1 + 2/D)."""
-    d = 2.0 / (r.req.gamma - 1.0) - r.req.dim
-    return d >= -1e-9
-
-
 def device_fields(r, device="cuda"):
     import torch
     q = r.req
@@ -156,14 +150,12 @@ def serve_pool(trace, budget_bytes, max_slots=256, ticks=8, precision=lbm.LBM_FP
     released.  progress_every > 0 prints a line to stderr every that many
     completions."""
     import torch
-    pending = sorted([r for r in trace if valid(r)], key=lambda r: r.arrival)
-    for r in trace:
-        if not valid(r):
-            r.ok, r.note = False, "rejected: gamma gives delta < 0"
+    pending = sorted(trace, key=lambda r: r.arrival)
     waiting = []
     resident = {}
     i = 0
     n_done = 0
+    n_valid = len(pending)
     stream = torch.cuda.Stream()
     with lbm.Pool(budget_bytes, max_slots, precision) as pool:
         pool.set_stream(stream)
@@ -174,24 +166,33 @@ def serve_pool(trace, budget_bytes, max_slots=256, ticks=8, precision=lbm.LBM_FP
             while i < len(pending) and (not realtime or pending[i].arrival <= now):
                 waiting.append(pending[i])
                 i += 1
-            # admission, FIFO with backfill
+            # admission, FIFO with backfill.  The library judges each request:
+            # a footprint of 0 means it would refuse it (EINVAL), e.g. a gamma
+            # that leaves delta < 0.  A request's device fields are built only
+            # once the pool has a slot and the arena space for it, so waiting
+            # requests hold no device memory.
             still = []
+            info = pool.info()
             for r in waiting:
-                if "fields" not in r.extra:  # built once, kept while it waits
-                    with torch.cuda.stream(stream):
-                        r.extra["fields"] = device_fields(r)
-                f = r.extra["fields"]
-                try:
-                    slot = pool.admit_dev(r.req, *f)
-                except lbm.LBMError as e:  # can never fit
-                    r.ok, r.note, r.done = False, f"rejected: {e}", now
+                need = lbm.lbm_pool_request_bytes(r.req, precision)
+                if need == 0 or need > info["budget_bytes"]:
+                    why = "invalid request" if need == 0 else "larger than the arena"
+                    r.ok, r.note, r.done = False, f"rejected: {why}", now
+                    n_valid -= 1
                     continue
+                if info["resident"] >= info["max_slots"] or need > info["largest_free_bytes"]:
+                    still.append(r)
+                    continue
+                with torch.cuda.stream(stream):
+                    f = device_fields(r)
+                slot = pool.admit_dev(r.req, *f)
+                del f  # copied into the pool (the stream orders the reuse)
                 if slot is None:
                     still.append(r)
                     continue
                 r.admitted = time.perf_counter() - t0
-                r.extra.pop("fields", None)  # copied into the pool
                 resident[slot] = r
+                info = pool.info()
             waiting = still
             if not resident:
                 if i < len(pending):
@@ -206,7 +207,7 @@ def serve_pool(trace, budget_bytes, max_slots=256, ticks=8, precision=lbm.LBM_FP
                 _finish(r, rho, t0)
                 pool.release(slot)
                 n_done += 1
-                _progress(progress_every, n_done, len(pending), t0, "FP32 pool")
+                _progress(progress_every, n_done, n_valid, t0, "FP32 pool")
         makespan = time.perf_counter() - t0
     return trace, makespan
 
@@ -220,16 +221,20 @@ def serve_sequential(trace, precision=lbm.LBM_FP64, realtime=True, progress_ever
     t0 = time.perf_counter()
     for n, r in enumerate(sorted(trace, key=lambda r: r.arrival)):
         _progress(progress_every, n, len(trace), t0, "one at a time")
-        if not valid(r):
-            r.ok, r.note = False, "rejected: gamma gives delta < 0"
-            continue
         now = time.perf_counter() - t0
         if realtime and r.arrival > now:
             time.sleep(r.arrival - now)
         q = r.req
         r.admitted = time.perf_counter() - t0
-        with lbm.Solver(q.dim, q.gamma, q.tau_f, q.tau_g, q.nx, q.ny, q.nz, bc=q.bc,
-                        precision=precision) as s:
+        try:
+            s = lbm.Solver(q.dim, q.gamma, q.tau_f, q.tau_g, q.nx, q.ny, q.nz, bc=q.bc,
+                           precision=precision)
+        except lbm.LBMError as e:  # the library refuses the request (EINVAL)
+            if e.code != lbm.LBM_EINVAL:
+                raise
+            r.ok, r.note, r.done, r.admitted = False, "rejected: invalid request", None, None
+            continue
+        with s:
             s.set_stream(stream)
             with torch.cuda.stream(stream):
                 f = device_fields(r)

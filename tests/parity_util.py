@@ -24,7 +24,7 @@ def gpu_run(dim, gamma, tf, tg, shape, fields, steps, bc=0, precision=lbm.LBM_FP
         s.init_fields(*fields)
         s.step(steps)
         rho, u, E = s.moments()
-        T = s.temperature(u, E)
+        T = s.temperature()
         tot = s.totals()
     return rho, u, T, tot
 

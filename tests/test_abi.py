@@ -117,3 +117,49 @@ def test_create_fd_refuses_half_storage():
     # valid in every other respect: half storage alone is refused
     assert lbm.lbm_create_fd_rc(2, 37, 1.4, 0.1, 0.1, 0.07, 8, 8, 1, 0,
                                 precision=lbm.LBM_FP16_SCALED) == lbm.LBM_EINVAL
+
+
+def _probe_declared():
+    text = open(os.path.join(ROOT, "include", "hbm_probe.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(hbm_probe_\w+)\s*\(", text, re.M))
+
+
+def test_hbm_probe_library_exports_and_checks_arguments():
+    names = _probe_declared()
+    assert {"hbm_probe_copy", "hbm_probe_read", "hbm_probe_variants"} <= names
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1608_06345_amd", "libhbmprobe.so"))
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    vp, sz, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
+    lib.hbm_probe_copy.argtypes = [vp, vp, sz, i32, vp]
+    lib.hbm_probe_read.argtypes = [vp, sz, i32, vp, vp]
+    lib.hbm_probe_variant_name.restype = ctypes.c_char_p
+    nv = lib.hbm_probe_variants(0)
+    assert nv >= 1 and lib.hbm_probe_variants(1) == nv and lib.hbm_probe_variants(2) == -1
+    assert lib.hbm_probe_variant_name(0, nv) is None
+    # argument checks come before any device call
+    assert lib.hbm_probe_copy(None, vp(4096), 1024, 0, None) == -1
+    assert lib.hbm_probe_copy(vp(8192), vp(4096), 1000, 0, None) == -1    # not a multiple of 16
+    assert lib.hbm_probe_copy(vp(8200), vp(4096), 1024, 0, None) == -1    # misaligned
+    assert lib.hbm_probe_copy(vp(4096 + 512), vp(4096), 1024, 0, None) == -1  # overlap
+    assert lib.hbm_probe_copy(vp(8192), vp(4096), 1024, nv, None) == -1   # no such variant
+    assert lib.hbm_probe_read(vp(4096), 1024, 0, None, None) == -1
+
+
+def test_pool_request_bytes_is_zero_for_any_invalid_request():
+    ok = lbm.make_request(3, 1.4, 0.65, 0.65, 16, 16, 16, steps=10)
+    assert lbm.lbm_pool_request_bytes(ok, lbm.LBM_FP32_DEV) >= 2 * 2 * 107 * 16 ** 3 * 4
+    # gamma 1.67 > 5/3 leaves delta < 0 in 3D (fine in 2D); gamma 5/3 snaps to delta 0
+    assert lbm.lbm_pool_request_bytes(
+        lbm.make_request(3, 1.67, 0.65, 0.65, 16, 16, 16, steps=10), lbm.LBM_FP32_DEV) == 0
+    assert lbm.lbm_pool_request_bytes(
+        lbm.make_request(2, 1.67, 0.7, 0.8, 16, 16, steps=10), lbm.LBM_FP32_DEV) > 0
+    assert lbm.lbm_pool_request_bytes(
+        lbm.make_request(3, 5.0 / 3.0, 0.65, 0.65, 16, 16, 16, steps=10), lbm.LBM_FP32_DEV) > 0
+    for bad in (lbm.make_request(2, 1.0, 0.7, 0.8, 16, 16, steps=10),
+                lbm.make_request(2, 1.4, 0.5, 0.8, 16, 16, steps=10),
+                lbm.make_request(2, 1.4, 0.7, 0.8, 16, 16, steps=-1),
+                lbm.make_request(2, 1.4, 0.7, 0.8, 0, 16, steps=10),
+                lbm.make_request(2, 1.4, 0.7, 0.8, 16, 16, bc=3, steps=10)):
+        assert lbm.lbm_pool_request_bytes(bad, lbm.LBM_FP32_DEV) == 0

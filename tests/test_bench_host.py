@@ -34,3 +34,19 @@ def test_headline_and_paths():
         assert ("finite-difference" in d) == ("dt" in p)
         assert ("LDS" in d) == (p.get("variant") == "split_lds")
     assert len(bench.kernel_source_hash()) == 16
+
+
+def test_gamma_five_thirds_path_keeps_h():
+    p = bench.PATHS["d3q107_fp32_gamma53"]
+    assert abs(p["gamma"] - 5.0 / 3.0) < 1e-15 and p["store"] == "fp32"
+    assert "delta 0)" in bench.describe("d3q107_fp32_gamma53", p)
+    # same bytes per update as gamma 1.4: h is stored and moved in full
+    assert bench.bytes_per_update(p["dim"], p["store"]) == 1712
+
+
+def test_every_path_has_an_accuracy_sample():
+    for name, p in bench.PATHS.items():
+        key = ("fd" if p.get("dt") else "lattice", p["dim"])
+        shape, steps = bench.ACCURACY_SAMPLES[key]
+        assert steps > 0 and shape[0] % 256 == 0  # whole tiles for the LDS kernels
+        assert (p["dim"] == 2) == (shape[2] == 1)

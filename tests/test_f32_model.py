@@ -1,0 +1,87 @@
+"""The float model of the step (f32_model.py) against the oracle on the
+shock-tube cases of shock_cases.py, on the CPU.
+
+What this pins down about the FP32 (and FP64) shock-tube bars:
+  * the model's algebra is the oracle's: evaluated in float64 it agrees
+    with the oracle to round-off on every case;
+  * evaluated in float32 -- in three orders (pairwise sums, sequential sums,
+    and one-ulp perturbations of every stored value after each collision) --
+    it differs from the oracle by the recorded gap, at least four orders of
+    magnitude above its float64 difference: float arithmetic itself makes
+    the gap;
+  * two float32 orders differ from each other by as much as either differs
+    from the oracle: the gap is rounding noise amplified by the shock, not a
+    bias any single evaluation shares;
+  * every bar sits within 2-40x of the recorded gap, and the recorded gaps
+    are what the model measures now (within 2x).
+"""
+import numpy as np
+import pytest
+
+from f32_model import DevModel
+from paper_1608_06345_amd.inputs import sod_fields
+from parity_util import oracle_run
+from shock_cases import CASES, FP32_BAR, FP32_GAP, FP64_BAR, FP64_GAP
+
+ORDERS = ("pairwise", "sequential", "perturbed")
+
+
+def _metric(a, b, kind):
+    if kind == "pointwise":
+        return max(float(np.max(np.abs(a[0] - b[0]) / b[0])),
+                   float(np.max(np.abs(a[1][0] - b[1][0]))),
+                   float(np.max(np.abs(a[2] - b[2]) / b[2])))
+    return max(float(np.sum(np.abs(x - y)) / np.sum(np.abs(y)))
+               for x, y in ((a[0], b[0]), (a[1][0], b[1][0]), (a[2], b[2])))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_float_families_set_the_shock_bars(name):
+    dim, gamma, tau, nx, left, right, steps, dt, kind = CASES[name]
+    f = sod_fields(dim, nx, 1, 1, left=left, right=right)
+    op = (True, False, False)
+    o = oracle_run(dim, gamma, tau, tau, (nx, 1, 1), f, steps, open_end=op, dt=dt)
+    ref = (o[0], o[1], o[2])
+    runs = {}
+    for ft in (np.float64, np.float32):
+        for order in ORDERS:
+            m = DevModel(dim, gamma, tau, tau, nx, 1, 1, open_end=op, dtype=ft, order=order,
+                         dt=dt)
+            m.init_fields(*f)
+            m.step(steps)
+            runs[(ft, order)] = m.moments()
+    gap = {ft: [_metric(runs[(ft, k)], ref, kind) for k in ORDERS]
+           for ft in (np.float64, np.float32)}
+    spread32 = _metric(runs[(np.float32, "pairwise")], runs[(np.float32, "sequential")], kind)
+    g64, g32 = max(gap[np.float64]), max(gap[np.float32])
+    print(f"\n{name} ({kind}): float64 gap {g64:.2e}, float32 gap {g32:.2e} "
+          f"(orders {[f'{v:.1e}' for v in gap[np.float32]]}), float32 pairwise vs "
+          f"sequential {spread32:.2e}")
+    # the algebra is the oracle's
+    assert g64 < 1e-10
+    # float arithmetic makes the gap
+    assert g32 > 1e4 * g64
+    # noise, not a shared bias: two float32 orders differ as much as from exact
+    assert spread32 > 0.1 * min(gap[np.float32])
+    # the recorded gaps are current, and the bars are a few times them
+    assert 0.5 * FP32_GAP[name] <= g32 <= 2 * FP32_GAP[name]
+    assert 0.5 * FP64_GAP[name] <= g64 <= 2 * FP64_GAP[name]
+    assert 2 * g32 <= FP32_BAR[name] <= 40 * g32
+    assert 2 * g64 <= FP64_BAR[name] <= 40 * g64
+
+
+def test_model_matches_oracle_on_a_smooth_field():
+    """Away from shocks the float32 model stays inside the FP32 bar of the
+    smooth fields (1e-5) over 200 steps, and float64 at round-off."""
+    from paper_1608_06345_amd.inputs import smooth_fields
+    shape = (48, 40, 1)
+    f = smooth_fields(2, *shape, seed=2, kmax=1)
+    o = oracle_run(2, 1.4, 0.7, 0.8, shape, f, 200)
+    for ft, tol in ((np.float64, 1e-12), (np.float32, 1e-5)):
+        m = DevModel(2, 1.4, 0.7, 0.8, *shape[:2], dtype=ft)
+        m.init_fields(*f)
+        m.step(200)
+        r, u, T = m.moments()
+        e = (np.max(np.abs(r - o[0]) / o[0]), np.max(np.abs(u - o[1])) / np.max(np.abs(o[1])),
+             np.max(np.abs(T - o[2]) / o[2]))
+        assert max(e) < tol, (ft, e)

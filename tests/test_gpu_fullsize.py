@@ -16,13 +16,15 @@ from paper_1608_06345_amd import lbm
 from paper_1608_06345_amd.inputs import smooth_fields
 from parity_util import TOL_FP32, TOL_FP64, oracle_sample
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(600)]
 
 CASES = {
     3: dict(shape=(256, 256, 256), gamma=1.4, tf=0.65, tg=0.65, seed=3),
     2: dict(shape=(4096, 4096, 1), gamma=1.4, tf=0.7, tg=0.8, seed=2),
 }
-STEPS = 4
+# steps before the sampled comparison: 20 in 3D (each sampled cell's
+# oracle window is 121^3 cells), 100 in 2D (601^2)
+STEPS = {3: 20, 2: 100}
 
 
 @pytest.fixture(scope="module", params=[3, 2])
@@ -32,16 +34,15 @@ def case(request):
     f = smooth_fields(dim, *c["shape"], seed=c["seed"])
     nx, ny, nz = c["shape"]
     if dim == 3:
-        centers = [(0, 0, 0), (255, 255, 255), (128, 3, 250), (7, 131, 64), (200, 100, 1),
-                   (254, 0, 127)]
+        centers = [(0, 0, 0), (255, 255, 255), (128, 3, 250), (7, 131, 64)]
     else:
         centers = [(0, 0), (4095, 4095), (2048, 5), (3, 2047), (1234, 3210), (4094, 1)]
-    ref = oracle_sample(dim, c["gamma"], c["tf"], c["tg"], f, c["shape"], centers, STEPS)
+    ref = oracle_sample(dim, c["gamma"], c["tf"], c["tg"], f, c["shape"], centers, STEPS[dim])
     return dim, c, f, centers, ref
 
 
-# half storage rounds each scaled deviation to 11 bits: after a few steps the
-# moments carry ~1e-5 of it (the 1000-step bars are in test_gpu_fp16)
+# half storage rounds each scaled deviation to 11 bits: after tens of steps
+# the moments carry ~1e-5 of it (the 1000-step bars are in test_gpu_fp16)
 TOL_FP16_SHORT = 1e-3
 
 
@@ -53,9 +54,9 @@ def test_full_size_sampled_cells(case, precision, tol):
     nx, ny, nz = c["shape"]
     with lbm.Solver(dim, c["gamma"], c["tf"], c["tg"], nx, ny, nz, precision=precision) as s:
         s.init_fields(*f)
-        s.step(STEPS)
+        s.step(STEPS[dim])
         rho, u, E = s.moments()
-        T = s.temperature(u, E)
+        T = s.temperature()
         m0, p0, e0 = s.totals()
         s.step(96)
         m1, p1, e1 = s.totals()
@@ -66,7 +67,8 @@ def test_full_size_sampled_cells(case, precision, tol):
         worst[0] = max(worst[0], abs(rho[cell] - r_o) / r_o)
         worst[1] = max(worst[1], np.max(np.abs(u[:, cell] - u_o)) / umax)
         worst[2] = max(worst[2], abs(T[cell] - T_o) / T_o)
-    print(f"\nPARITY full-size D{dim} precision={precision} sampled rho/u/T={worst}")
+    print(f"\nPARITY full-size D{dim} {STEPS[dim]} steps precision={precision} "
+          f"sampled rho/u/T={worst}")
     assert max(worst) <= tol, worst
     # conservation over 96 further steps (energy only where tau_f = tau_g)
     # (half storage rounds every stored value independently each step: the

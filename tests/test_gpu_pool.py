@@ -53,7 +53,7 @@ def _alone(req, f, precision, ticks=5, eager=False):
         s = pool.admit(req, *f)
         _run_to_end(pool, [s], ticks, eager)
         assert pool.steps_done(s) == req.steps
-        return pool.moments(s)
+        return pool.moments(s) + (pool.temperature(s),)
 
 
 @pytest.mark.parametrize("precision", [lbm.LBM_FP32_DEV, lbm.LBM_FP64])
@@ -76,7 +76,7 @@ def test_alone_equals_mix_bitwise(precision):
             pool.run(7)
             for s in pool.poll():
                 k = [kk for kk, ss in slots.items() if ss == s][0]
-                results[k] = pool.moments(s)
+                results[k] = pool.moments(s) + (pool.temperature(s),)
                 pool.release(s)
         assert len(results) == len(reqs)
     for k, (a, b) in enumerate(zip(alone, [results[i] for i in range(len(reqs))])):
@@ -98,15 +98,16 @@ def test_pool_matches_single_solve_and_oracle(precision, tol):
     for req, f in _requests()[:2] + _requests()[4:5]:
         dim = req.dim
         shape = (req.nx, req.ny, req.nz)
-        rho, u, E = _alone(req, f, precision)
+        rho, u, E, T = _alone(req, f, precision)
         with lbm.Solver(dim, req.gamma, req.tau_f, req.tau_g, *shape, bc=req.bc,
                         precision=precision) as s:
             s.init_fields(*f)
             s.step(req.steps)
             r2, u2, E2 = s.moments()
-            T = s.temperature(u, E)
+            T2 = s.temperature()
         # same kernels' arithmetic: identical to the single-solve path
         assert np.array_equal(rho, r2) and np.array_equal(u, u2) and np.array_equal(E, E2)
+        assert np.array_equal(T, T2)
         o = oracle_run(dim, req.gamma, req.tau_f, req.tau_g, shape, f, req.steps)
         assert_close((rho, u, T), o, tol, f"pool D{dim}")
 

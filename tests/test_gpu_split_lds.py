@@ -71,7 +71,7 @@ def test_lds_full_size_sampled_cells(precision, tol):
         s.init_fields(*f)
         s.step(steps)
         rho, u, E = s.moments()
-        T = s.temperature(u, E)
+        T = s.temperature()
     umax = max(np.max(np.abs(r[1])) for r in ref)
     worst = [0.0, 0.0, 0.0]
     for cen, (r_o, u_o, T_o) in zip(centers, ref):
