@@ -56,7 +56,8 @@ enum lbm_status {
     LBM_EDEVICE = -3,    /* a HIP runtime call failed */
     LBM_ESTATE = -4,     /* call out of order (e.g. step before init) */
     LBM_ENONFINITE = -5, /* a conservation total is NaN or infinite */
-    LBM_EBUSY = -6       /* pool: no free slot or arena space right now */
+    LBM_EBUSY = -6,      /* pool: no free slot or arena space right now */
+    LBM_ESCRATCH = -7    /* grid too large for lbm_moments_noalloc's scratch */
 };
 
 enum lbm_velocity_set { LBM_D2Q37 = 37, LBM_D3Q107 = 107 };
@@ -227,6 +228,18 @@ int lbm_moments_dev(lbm_handle h, double *rho, double *u, double *E);
 int lbm_temperature(lbm_handle h, double *T);
 /* Same into a device array, asynchronous on the handle's stream. */
 int lbm_temperature_dev(lbm_handle h, double *T);
+
+/* lbm_moments without any device allocation, for callers that cannot
+ * allocate device memory (tight serving loops retiring results, harnesses
+ * that forbid allocation).  Same arguments, results (bit for bit) and errors
+ * as lbm_moments; the fields are staged in a fixed 64 MiB device array that
+ * the library holds on each device it runs on until the process ends,
+ * instead of a buffer allocated per call.  Limit: (2 + dim) * ncells * 8
+ * bytes <= 64 MiB, i.e. ncells <= 2097152 in 2D and 1677721 in 3D; larger
+ * grids return LBM_ESCRATCH.  Every call on one device shares that device's
+ * array: calls that overlap on one device (from two threads, or on two
+ * streams) race.  Synchronous, so not for use under graph capture. */
+int lbm_moments_noalloc(lbm_handle h, double *rho, double *u, double *E);
 
 /* Domain totals of S_n in FP64, from the Sec. II moments summed over every
  * cell: mass = sum rho, mom[k] = sum rho u_k

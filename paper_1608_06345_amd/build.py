@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "liblbm.so")
 PROBE_LIB = os.path.join(HERE, "libhbmprobe.so")
-SOURCES = ["kernels.hip", "fd.hip", "api.hip", "pool.hip", "lattice.cpp"]
+SOURCES = ["kernels.hip", "fd.hip", "api.hip", "pool.hip", "noalloc.hip", "lattice.cpp"]
 PROBE_SOURCES = ["hbm_probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -162,6 +162,7 @@ const char* lbm_strerror(int code) {
         case LBM_ESTATE: return "call out of order (no initial fields)";
         case LBM_ENONFINITE: return "non-finite conservation total";
         case LBM_EBUSY: return "no free pool slot or arena space now";
+        case LBM_ESCRATCH: return "grid exceeds the no-allocation readout's 64 MiB scratch";
         default: return "unknown status";
     }
 }

@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ESTATE, LBM_ENONFINITE = 0, -1, -2, -3, -4, -5
 LBM_EBUSY = -6
+LBM_ESCRATCH = -7
 LBM_D2Q37, LBM_D3Q107 = 37, 107
 LBM_BC_PERIODIC, LBM_BC_ZERO_GRADIENT = 0, 1
 LBM_FP64, LBM_FP32_DEV, LBM_FP16_SCALED = 0, 1, 2
@@ -94,6 +95,7 @@ def _load():
         "lbm_step": [vp, i64],
         "lbm_moments": [vp, dp, dp, dp],
         "lbm_moments_dev": [vp, vp, vp, vp],
+        "lbm_moments_noalloc": [vp, dp, dp, dp],
         "lbm_temperature": [vp, dp],
         "lbm_temperature_dev": [vp, vp],
         "lbm_totals": [vp, dp, dp, dp],
@@ -258,6 +260,24 @@ def lbm_moments(h):
     rho, u, E = np.empty(n), np.empty((inf["dim"], n)), np.empty(n)
     _check(_lib.lbm_moments(h, _dp(rho), _dp(u), _dp(E)), "lbm_moments")
     return rho, u, E
+
+
+def lbm_moments_noalloc(h):
+    """As lbm_moments, staged through the library's fixed device scratch
+    (no device allocation)."""
+    inf = lbm_get_info(h)
+    n = inf["nx"] * inf["ny"] * inf["nz"]
+    rho, u, E = np.empty(n), np.empty((inf["dim"], n)), np.empty(n)
+    _check(_lib.lbm_moments_noalloc(h, _dp(rho), _dp(u), _dp(E)), "lbm_moments_noalloc")
+    return rho, u, E
+
+
+def lbm_moments_noalloc_rc(h):
+    """Raw status code of lbm_moments_noalloc (for error-path tests)."""
+    inf = lbm_get_info(h)
+    n = inf["nx"] * inf["ny"] * inf["nz"]
+    rho, u, E = np.empty(n), np.empty((inf["dim"], n)), np.empty(n)
+    return _lib.lbm_moments_noalloc(h, _dp(rho), _dp(u), _dp(E))
 
 
 def lbm_moments_dev(h, rho, u, E):
