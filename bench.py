@@ -165,12 +165,15 @@ def run_path(name, p, steps, warmup):
     }
 
 
-def hbm_ceiling(nbytes, reps=5):
+def hbm_ceiling(nbytes, reps=5, pattern_cells=None, pattern_nx=None):
     """What plain data movement reaches on this device (libhbmprobe.so): a
     streaming copy of nbytes / 2 bytes (nbytes of HBM traffic) and a
     read-only sweep of nbytes, each launch shape timed over `reps` launches
     with HIP events on the stream they run on, after one untimed launch.
-    GB/s counts the bytes each launch must move (copy: read + write)."""
+    GB/s counts the bytes each launch must move (copy: read + write).
+    With pattern_cells, also the D3Q107 step's own access shape with no
+    arithmetic (hbm_probe_planes): 214 planes of that many cells, rows of
+    pattern_nx."""
     import ctypes
 
     import torch
@@ -220,6 +223,32 @@ def hbm_ceiling(nbytes, reps=5):
     torch.cuda.empty_cache()
     out["copy_gbs"] = max(out["copy"].values())
     out["read_gbs"] = max(out["read"].values())
+    if pattern_cells:
+        lib.hbm_probe_planes.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int64, i32, vp]
+        n = 214 * pattern_cells
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+
+        def planes(a, b):
+            rc = lib.hbm_probe_planes(ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(a.data_ptr()),
+                                      pattern_cells, pattern_cells, pattern_nx, sp)
+            if rc != 0:
+                raise RuntimeError(f"hbm_probe_planes: status {rc}")
+
+        planes(src, dst)
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for k in range(reps):
+            planes(src, dst) if k % 2 == 0 else planes(dst, src)
+        end.record(stream)
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(end) / reps
+        out["step_pattern_gbs"] = round(2 * 214 * pattern_cells * 4 / (ms * 1e-3) / 1e9, 1)
+        out["step_pattern_ms"] = round(ms, 4)
+        del src, dst
+        torch.cuda.empty_cache()
     return out
 
 
@@ -319,9 +348,11 @@ def _gpu_sample(p, shape, steps, store=None, fields=None):
 
 
 # Same-recipe samples for the per-path error against the oracle: small
-# enough for the host, rows a multiple of 256 cells (the LDS kernels' tile).
+# enough for the host, rows of whole LDS tiles (128 cells for the staged pull, 256
+# for the finite-difference update), and for 3D few enough steps that seed 3's
+# velocity modes are still alive (max |u| ~1e-2).
 ACCURACY_SAMPLES = {
-    ("lattice", 3): ((256, 24, 24), 80),
+    ("lattice", 3): ((128, 64, 64), 30),
     ("lattice", 2): ((256, 256, 1), 300),
     ("fd", 3): ((256, 16, 16), 100),
     ("fd", 2): ((256, 128, 1), 300),
@@ -508,17 +539,28 @@ def main():
     ap.add_argument("--no-ceiling", action="store_true",
                     help="skip the HBM copy / read ceiling probe")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
-                    help="only copy a device buffer of BYTES bytes 5 times (a plain copy "
-                         "kernel of known size, to scale the HBM byte counters) and exit")
+                    help="only copy BYTES bytes 5 times with the streaming copy of "
+                         "libhbmprobe.so (a plain copy kernel of known size, to scale the "
+                         "HBM byte counters) and exit")
     args = ap.parse_args()
     if args.copy_probe:
+        import ctypes
+
         import torch
-        a = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
+        lib = ctypes.CDLL(os.path.join(ROOT, "paper_1608_06345_amd", "libhbmprobe.so"))
+        lib.hbm_probe_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                       ctypes.c_int, ctypes.c_void_p]
+        n = args.copy_probe // 16 * 16
+        a = torch.ones(n // 4, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
-        for _ in range(5):
-            b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes": args.copy_probe, "launches": 5}))
+        for _ in range(5):  # variant 2: 4 x 16 B per lane, non-temporal
+            rc = lib.hbm_probe_copy(ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(a.data_ptr()),
+                                    n, 2, None)
+            if rc != 0:
+                raise RuntimeError(f"hbm_probe_copy: status {rc}")
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n, "launches": 5, "kernel": "k_probe_copy<4, true>"}))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the solver has no multi-GPU path "
@@ -545,9 +587,12 @@ def main():
     algo_bytes = res["bytes_per_update"] * res["cells"]
     ceiling = None
     if not args.no_ceiling and not args.serving_only:
-        ceiling = hbm_ceiling(algo_bytes)
-        print(f"# HBM ceiling: copy {ceiling['copy_gbs']} GB/s, read {ceiling['read_gbs']} GB/s",
-              file=sys.stderr, flush=True)
+        three_d = head["dim"] == 3
+        ceiling = hbm_ceiling(algo_bytes, pattern_cells=res["cells"] if three_d else None,
+                              pattern_nx=head["shape"][0] if three_d else None)
+        print(f"# HBM ceiling: copy {ceiling['copy_gbs']} GB/s, read {ceiling['read_gbs']} GB/s, "
+              f"step access pattern {ceiling.get('step_pattern_gbs')} GB/s", file=sys.stderr,
+              flush=True)
     out = {
         "metric": "MLUPS (million lattice-cell updates per second)",
         "value": res["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
@@ -579,6 +624,9 @@ def main():
         out["roofline"].update({
             "copy_gbs": ceiling["copy_gbs"], "read_gbs": ceiling["read_gbs"],
             "frac_of_copy": round(res["gbs"] / ceiling["copy_gbs"], 4),
+            "step_pattern_gbs": ceiling.get("step_pattern_gbs"),
+            "frac_of_step_pattern": (round(res["gbs"] / ceiling["step_pattern_gbs"], 4)
+                                     if ceiling.get("step_pattern_gbs") else None),
             "ceiling_probe": ceiling})
     if args.serving_only:
         servers = ("pool", "sequential") if args.serving_only == "both" else (args.serving_only,)

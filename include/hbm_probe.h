@@ -14,6 +14,7 @@
 #define HBM_PROBE_H
 
 #include <stddef.h>
+#include <stdint.h>
 
 #ifdef __cplusplus
 extern "C" {
@@ -37,6 +38,19 @@ int hbm_probe_copy(void *dst, const void *src, size_t bytes, int variant,
  * written in practice.  HBM traffic: bytes. */
 int hbm_probe_read(const void *src, size_t bytes, int variant, float *sink,
                    void *stream);
+
+/* The memory access shape of the D3Q107 split step kernel, with no
+ * arithmetic: 214 planes of `cells` floats, plane k starting at
+ * src + k * stride floats, are read and written to the same places of dst.
+ * A wave serves 32 cells of one x-row of nx cells (lanes 0..31 plane 2i,
+ * lanes 32..63 plane 2i + 1 of each pair, one 4-byte value per lane and
+ * plane), loading all 214 values before storing them; workgroups of four
+ * waves are dealt to the XCDs by whole rows, as the step does.  nx a
+ * multiple of 128, cells a multiple of nx, stride >= cells, both buffers
+ * 16-byte aligned, 214 * stride floats each and disjoint.  HBM traffic:
+ * 2 * 214 * cells * 4 bytes, the step's algorithmic bytes. */
+int hbm_probe_planes(void *dst, const void *src, int64_t cells, int64_t stride,
+                     int nx, void *stream);
 
 #ifdef __cplusplus
 }

@@ -35,7 +35,7 @@ bool delta_of(double gamma, int dim, double* delta) {
 
 struct Shape {
     int dim, q, precision;
-    int64_t nx, ny, nz, N;
+    int64_t nx, ny, nz, N, P;  // P: plane stride in cells
     size_t elem;
 };
 
@@ -49,11 +49,14 @@ int check_shape(int dim, int velocity_set, int precision, int64_t nx, int64_t ny
     if (nx < 1 || ny < 1 || nz < 1) return LBM_EINVAL;
     if (dim == 2 && nz != 1) return LBM_EINVAL;
     const size_t elem = precision == LBM_FP64 ? 8 : (precision == LBM_FP32_DEV ? 4 : 2);
-    // one population plane must stay addressable with 32-bit byte offsets
-    // (the kernels add a plane offset to a cell offset in 32 bits)
+    // one population plane (its stride included) must stay addressable with
+    // 32-bit byte offsets: the kernels add a plane offset to a cell offset in
+    // 32 bits
     if (nx > (1LL << 31) || ny > (1LL << 31) || nz > (1LL << 31)) return LBM_EINVAL;
     const double N = (double)nx * (double)ny * (double)nz;
     if (N * (double)elem > 2147483647.0) return LBM_EINVAL;
+    const int64_t P = lbm::plane_stride(nx * ny * nz, elem, dim);
+    if ((double)P * (double)elem > 2147483647.0) return LBM_EINVAL;
     s->dim = dim;
     s->q = velocity_set;
     s->precision = precision;
@@ -61,6 +64,7 @@ int check_shape(int dim, int velocity_set, int precision, int64_t nx, int64_t ny
     s->ny = ny;
     s->nz = nz;
     s->N = nx * ny * nz;
+    s->P = P;
     s->elem = elem;
     return LBM_OK;
 }
@@ -68,7 +72,7 @@ int check_shape(int dim, int velocity_set, int precision, int64_t nx, int64_t ny
 int read_blocks_of(int64_t N) { return (int)((N + lbm::kReadBlock - 1) / lbm::kReadBlock); }
 
 size_t footprint(const Shape& s) {
-    const size_t side = 2 * (size_t)s.q * (size_t)s.N * s.elem;
+    const size_t side = 2 * (size_t)s.q * (size_t)s.P * s.elem;
     const size_t partial = (size_t)read_blocks_of(s.N) * (s.dim + 2) * sizeof(double);
     return 2 * side + partial + 8 * sizeof(double);
 }
@@ -79,6 +83,7 @@ lbm::StepArgs step_args(const lbm_solver* h, const void* src, void* dst, bool st
     a.src = src;
     a.dst = dst;
     a.N = h->N;
+    a.P = h->P;
     a.nx = (int32_t)h->nx;
     a.ny = (int32_t)h->ny;
     a.nz = (int32_t)h->nz;
@@ -104,6 +109,7 @@ int readout(lbm_solver* h, double* rho, double* u, double* E, double* T, bool to
         a.stream = h->initial ? 0 : 1;
     }
     a.N = h->N;
+    a.P = h->P;
     a.nx = (int32_t)h->nx;
     a.ny = (int32_t)h->ny;
     a.nz = (int32_t)h->nz;
@@ -249,6 +255,7 @@ int create_solver(int dim, int velocity_set, double gamma, double tau_f, double 
     h->ny = ny;
     h->nz = nz;
     h->N = s.N;
+    h->P = s.P;
     h->bc = bc;
     h->gamma = gamma;
     h->delta = delta;
@@ -258,7 +265,7 @@ int create_solver(int dim, int velocity_set, double gamma, double tau_f, double 
     h->dt = dt;
     h->lat = &lbm::lattice_tables(dim);
     h->elem = s.elem;
-    h->buf_bytes = 2 * (size_t)s.q * (size_t)s.N * s.elem;
+    h->buf_bytes = 2 * (size_t)s.q * (size_t)s.P * s.elem;
     h->read_blocks = read_blocks_of(s.N);
     // one lane per cell keeps all 2Q populations in registers; for D3Q107
     // that is 214 values, so the 3D kernels split g and h across lane pairs
@@ -273,7 +280,7 @@ int create_solver(int dim, int velocity_set, double gamma, double tau_f, double 
     e = hipMalloc(&h->buf[0], h->buf_bytes);
     if (e == hipSuccess) e = hipMalloc(&h->buf[1], h->buf_bytes);
     if (e == hipSuccess && h->scheme)
-        e = hipMalloc(&h->fd_record, lbm::fd_record_bytes(dim, precision, s.N));
+        e = hipMalloc(&h->fd_record, lbm::fd_record_bytes(dim, precision, s.P));
     if (e == hipSuccess)
         e = hipMalloc((void**)&h->partials, (size_t)h->read_blocks * (dim + 2) * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&h->totals, 8 * sizeof(double));
@@ -284,7 +291,7 @@ int create_solver(int dim, int velocity_set, double gamma, double tau_f, double 
         return dev_err(e);
     }
     h->stream = h->own_stream;
-    h->device_bytes = footprint(s) + (h->scheme ? lbm::fd_record_bytes(dim, precision, s.N) : 0);
+    h->device_bytes = footprint(s) + (h->scheme ? lbm::fd_record_bytes(dim, precision, s.P) : 0);
     *out = h;
     return LBM_OK;
 }
@@ -370,8 +377,8 @@ int lbm_init_fields_dev(lbm_handle h, const double* rho, const double* u, const 
     if (!h || !rho || !u || !T) return LBM_EINVAL;
     // S_0 into side 0; P_0 = Collide(S_0) into side 1 (same collision code as
     // every step, with the pull switched off).
-    LBM_HIP(lbm::launch_init(h->dim, h->precision, h->buf[0], rho, u, T, h->N, 0.5 * h->delta,
-                             h->lat->r, h->lat->w_group, h->stream));
+    LBM_HIP(lbm::launch_init(h->dim, h->precision, h->buf[0], rho, u, T, h->N, h->P,
+                             0.5 * h->delta, h->lat->r, h->lat->w_group, h->stream));
     if (h->scheme) {  // finite differences keep S_n itself
         h->fd_record_valid = false;
         h->cur = 0;

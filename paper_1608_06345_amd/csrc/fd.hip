@@ -36,7 +36,8 @@ namespace {
 
 using namespace core;
 
-// Record fields, each a plane of N values in the arithmetic type:
+// Record fields, each a plane (stride P, the population planes' stride) of
+// values in the arithmetic type:
 //   0 drho (deviation storage) or rho; 1..D u; D+1 t = T - 1; D+2 kappa rho;
 //   deviation storage only: D+3 dm_g, D+4 .. 2D+3 dj_g, 2D+4 de_g, 2D+5 dm_h.
 template <int D, bool DEV>
@@ -81,6 +82,7 @@ __device__ __forceinline__ void target_residuals(const Equilibrium<D, T, true>& 
                                                  const Physics& a, T arho, T beta, T want_m,
                                                  const T* want_j, T want_e, T je_on, T& dm,
                                                  T* dj, T& de) {
+#pragma clang fp contract(off)
     constexpr VelSet<D> V = kVelSet<D>;
     constexpr int G = VelSet<D>::G;
     T sm = 0, sjx = 0, sjy = 0, sjz = 0, se = 0;
@@ -94,23 +96,20 @@ __device__ __forceinline__ void target_residuals(const Equilibrium<D, T, true>& 
             constexpr int i = first + 2 * decltype(Pi)::value;
             constexpr Vel v = V.v[i];
             const T c = eq.template dot<v.x, v.y, v.z>();
-            const T c2 = c * c;
-            const T even = A0 + c2 * (A2 + c2 * T(1.0 / 24.0));
-            const T odd = c * (A1 + c2 * T(1.0 / 6.0));
-            const T tp = w * (arho * (even + odd) + beta);
-            const T tm = w * (arho * (even - odd) + beta);
+            T tp, tm;
+            pair_targets(A0, A1, A2, c, w, arho, beta, tp, tm);
             const T sum = tp + tm;
             const T dif = tp - tm;
             sm += sum;
-            if constexpr (v.x != 0) sjx += T(v.x) * dif;
-            if constexpr (v.y != 0) sjy += T(v.y) * dif;
-            if constexpr (D == 3 && v.z != 0) sjz += T(v.z) * dif;
-            se += T(V.qn[g]) * sum;
+            if constexpr (v.x != 0) sjx = fmadd(T(v.x), dif, sjx);
+            if constexpr (v.y != 0) sjy = fmadd(T(v.y), dif, sjy);
+            if constexpr (D == 3 && v.z != 0) sjz = fmadd(T(v.z), dif, sjz);
+            se = fmadd(T(V.qn[g]), sum, se);
         });
     });
     T A0, A1, A2;
     eq.template coef<0>(A0, A1, A2);
-    sm += weight<T>(a, 0) * (arho * A0 + beta);
+    sm += rest_target(A0, weight<T>(a, 0), arho, beta);
     dm = want_m - sm;
     de = je_on * (want_e - se);
     dj[0] = je_on * (want_j[0] - sjx);
@@ -157,14 +156,15 @@ __device__ __forceinline__ void write_record(typename P::T s0, typename P::T sx,
 
 template <int D, class P>
 __global__ __launch_bounds__(256) void k_fd_moments(const void* __restrict__ src_v,
-                                                    typename P::T* __restrict__ rec, int64_t N,
+                                                    typename P::T* __restrict__ rec,
+                                                    int64_t cells, int64_t N,
                                                     const Physics ph) {
     using T = typename P::T;
     using S = typename P::S;
     constexpr VelSet<D> V = kVelSet<D>;
     constexpr int Q = VelSet<D>::Q;
     const int64_t cell = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (cell >= N) return;  // lanes are independent here
+    if (cell >= cells) return;  // lanes are independent here (N: the plane stride)
     const S* src = static_cast<const S*>(src_v);
     // running sums over the centre values (moment_sums, streamed)
     T s0 = 0, sx = 0, sy = 0, sz = 0, se = 0, sh = 0;
@@ -268,20 +268,21 @@ struct FdCell {
         T A0, A1, A2;
         eq.template coef<V.qn[g]>(A0, A1, A2);
         const T w = weight<T>(ph, g);
-        T pg;  // P~ for this population
+        // the targets exactly as relax<...> and target_residuals form them
+        T tg, th;
         if constexpr (i == 0) {
-            pg = A0;
+            tg = rest_target(A0, w, rho, beta_g);
+            th = rest_target(A0, w, arho_h, beta_h);
         } else {
             constexpr int first = (i - group_start<D>(g)) % 2 == 0 ? i : i - 1;
             constexpr Vel vf = V.v[first];
             const T c = eq.template dot<vf.x, vf.y, vf.z>();
-            const T c2 = c * c;
-            const T even = A0 + c2 * (A2 + c2 * T(1.0 / 24.0));
-            const T odd = c * (A1 + c2 * T(1.0 / 6.0));
-            pg = i == first ? even + odd : even - odd;
+            T gp, gm, hp, hm;
+            pair_targets(A0, A1, A2, c, w, rho, beta_g, gp, gm);
+            pair_targets(A0, A1, A2, c, w, arho_h, beta_h, hp, hm);
+            tg = i == first ? gp : gm;
+            th = i == first ? hp : hm;
         }
-        T tg = w * (rho * pg + beta_g);
-        T th = w * (arho_h * pg + beta_h);
         if constexpr (DEV && i == 0) {
             tg += dm - de;
             th += dmh;
@@ -299,11 +300,11 @@ struct FdCell {
         T xh = from_store<P>(at(H{}, Z{}, Z{}), ph, g);
         if constexpr (l1_of(v) != 0) {
             const T kc = T(3 * l1_of(v)) * cs;
-            xg = (xg - kc * xg) + omf * (tg - xg);
-            xh = (xh - kc * xh) + omg * (th - xh);
+            xg = relax_value(xg, tg, omf, kc);
+            xh = relax_value(xh, th, omg, kc);
         } else {
-            xg = xg + omf * (tg - xg);
-            xh = xh + omg * (th - xh);
+            xg = relax_value(xg, tg, omf);
+            xh = relax_value(xh, th, omg);
         }
         T nbg = T(0), nbh = T(0);
         static_for<0, D>([&](auto A) {
@@ -373,7 +374,7 @@ __global__ __launch_bounds__(256) void k_fd_update(const void* __restrict__ src_
                                                    typename P::T* __restrict__ rec,
                                                    const StepArgs a) {
     using S = typename P::S;
-    const int64_t N = a.N;
+    const int64_t N = a.P;  // plane stride (record and populations)
     int xt, cy, cz;
     if (!sweep_tile(a, (int)blockIdx.x, xt, cy, cz)) return;
     const int cx = xt * 256 + (int)threadIdx.x;
@@ -449,7 +450,7 @@ __global__ __launch_bounds__(256) void k_fd_update_lds(const void* __restrict__ 
     constexpr int SL = kLdsSlots<D>;  // LDS slots of one population
     static_assert(PB == 1 || PB == 2, "one or two populations per phase");
     __shared__ __attribute__((aligned(16))) S lds[PB * SL];
-    const int64_t N = a.N;
+    const int64_t N = a.P;  // plane stride (record and populations)
     int xt, cy, cz;
     // the whole workgroup leaves together (it meets at barriers below)
     if (!sweep_tile(a, (int)blockIdx.x, xt, cy, cz)) return;
@@ -617,7 +618,7 @@ hipError_t fd_two_pass_impl(const StepArgs& a0, void* rec_v, bool record_valid, 
     const int tiles = (int)((a.N + 255) / 256);
     if (!record_valid) {
         hipError_t e = launch_kernel(&k_fd_moments<D, P>, dim3(tiles), dim3(256), s, a.src, rec,
-                                     a.N, a.ph);
+                                     a.N, a.P, a.ph);
         if (e != hipSuccess) return e;
     }
     // one x-row tile of one chunk's planes (at most 14 populations, g and h)
@@ -654,11 +655,11 @@ hipError_t fd_two_pass_impl(const StepArgs& a0, void* rec_v, bool record_valid, 
 
 }  // namespace
 
-size_t fd_record_bytes(int dim, int precision, int64_t N) {
+size_t fd_record_bytes(int dim, int precision, int64_t P) {
     const bool dev = precision != LBM_FP64;  // record (deviation storage: residuals too)
     const int fields = dim == 2 ? (dev ? kRecFields<2, true> : kRecFields<2, false>) + kAccFields<2>
                                 : (dev ? kRecFields<3, true> : kRecFields<3, false>) + kAccFields<3>;
-    return (size_t)fields * (size_t)N * (precision == LBM_FP64 ? 8 : 4);
+    return (size_t)fields * (size_t)P * (precision == LBM_FP64 ? 8 : 4);
 }
 
 hipError_t launch_fd_two_pass(int dim, int precision, const StepArgs& a, void* record,

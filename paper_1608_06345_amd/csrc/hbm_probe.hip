@@ -1,5 +1,6 @@
 // HBM ceiling probes (include/hbm_probe.h): a streaming copy and a read-only
-// sweep, 16 bytes per lane access, in a few launch shapes.  Workgroup b
+// sweep, 16 bytes per lane access, in a few launch shapes; and the D3Q107
+// step's own memory access shape with no arithmetic.  Workgroup b
 // covers U * 256 consecutive 16-byte elements, lane t the elements
 // b U 256 + k 256 + t (k < U): every wave access is one contiguous 1 KiB, and
 // a lane has U loads in flight before its first store.
@@ -51,6 +52,35 @@ __global__ __launch_bounds__(256) void k_probe_read(const f4* __restrict__ src, 
     }
     // -0x1.fffffep127 is reached by no sum of ordinary data
     if (acc == -3.40282347e38f) sink[threadIdx.x] = acc;
+}
+
+// The memory access shape of the D3Q107 split step kernel with no
+// arithmetic: a workgroup of four waves serves 128 cells of one x-row, a
+// wave 32 of them, lanes 0..31 reading plane 2i and lanes 32..63 plane 2i+1
+// of each of the 107 population pairs (one 4-byte value per lane and
+// plane), all loads issued before the stores; workgroup b runs on XCD b % 8,
+// whose turns walk whole rows.  Each value is written back to the same
+// place in the other buffer.
+constexpr int kPatternPlanes = 214;
+
+__global__ __launch_bounds__(256) void k_probe_planes(const float* __restrict__ src,
+                                                      float* __restrict__ dst, int64_t stride,
+                                                      int rows, int tiles_per_row, int nx) {
+    const int b = (int)blockIdx.x, j = b >> 3;
+    const int row = (j / tiles_per_row) * 8 + (b & 7);
+    if (row >= rows) return;
+    const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    const int x = (j % tiles_per_row) * 128 + wave * 32 + (lane & 31);
+    const int64_t cell = (int64_t)row * nx + x;
+    const int role = lane >> 5;
+    float v[kPatternPlanes / 2];
+#pragma unroll
+    for (int i = 0; i < kPatternPlanes / 2; ++i) v[i] = src[(int64_t)(2 * i + role) * stride + cell];
+    // a data-dependent factor of one keeps every store a computed value
+    const float one = v[0] == -3.40282347e38f ? 0.5f : 1.0f;
+#pragma unroll
+    for (int i = 0; i < kPatternPlanes / 2; ++i)
+        __builtin_nontemporal_store(v[i] * one, dst + (int64_t)(2 * i + role) * stride + cell);
 }
 
 struct Variant {
@@ -126,6 +156,25 @@ int hbm_probe_copy(void* dst, const void* src, size_t bytes, int variant, void* 
     if (d < s + bytes && s < d + bytes) return -1;  // overlapping ranges
     const hipError_t e = launch_copy(variant, static_cast<f4*>(dst), static_cast<const f4*>(src),
                                      (int64_t)(bytes / 16), static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? 0 : -3;
+}
+
+int hbm_probe_planes(void* dst, const void* src, int64_t cells, int64_t stride, int nx,
+                     void* stream) {
+    if (!dst || !src || cells < 1 || nx < 128 || nx % 128 || cells % nx || stride < cells)
+        return -1;
+    if (!aligned16(dst) || !aligned16(src)) return -1;
+    const size_t bytes = (size_t)kPatternPlanes * (size_t)stride * sizeof(float);
+    const char* d = static_cast<const char*>(dst);
+    const char* sp = static_cast<const char*>(src);
+    if (d < sp + bytes && sp < d + bytes) return -1;
+    const int64_t rows = cells / nx;
+    const int tiles = nx / 128;
+    const int64_t grid = 8 * (int64_t)tiles * ((rows + 7) / 8);
+    if (grid > 0x7fffffff || rows > 0x7fffffff) return -1;
+    const hipError_t e = launch(reinterpret_cast<const void*>(&k_probe_planes), dim3((unsigned)grid),
+                                static_cast<hipStream_t>(stream), static_cast<const float*>(src),
+                                static_cast<float*>(dst), stride, (int)rows, tiles, nx);
     return e == hipSuccess ? 0 : -3;
 }
 

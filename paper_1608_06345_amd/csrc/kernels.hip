@@ -2,8 +2,8 @@
 // the fused finite-difference step (Sec. III; its two-pass form is in
 // fd.hip), and the FP64 readout / conservation reductions.
 //
-// Data layout in HBM (one ping-pong side): [Q][2][N] -- for population i the
-// g plane (N values, x fastest) and then the h plane.  Every plane is read
+// Data layout in HBM (one ping-pong side): [Q][2][P] -- for population i the
+// g plane (N values, x fastest, in a slot of P >= N) and then the h plane.  Every plane is read
 // once and written once per step: one HBM read and one HBM write per
 // population per cell.
 //
@@ -83,7 +83,7 @@ void k_step(const StepArgs a) {
     RowOffsets<S> o;
     bool active;
     if (!row_item<D, S, 64>(a, (int)threadIdx.x & 63, 0u, o, active)) return;
-    const uint32_t plane = (uint32_t)a.N * (uint32_t)sizeof(S);
+    const uint32_t plane = (uint32_t)a.P * (uint32_t)sizeof(S);
     T g[Q], h[Q];
     load_lane<D, P>(static_cast<const char*>(a.src), plane, o, g, h, a.ph);
     collide_lane<D, P>(g, h, a.ph);
@@ -106,7 +106,7 @@ void k_step_split(const StepArgs a) {
     constexpr int Q = VelSet<D>::Q;
     const int lane = (int)threadIdx.x & 63;
     const int role = lane >> 5;  // 0: g, 1: h
-    const uint32_t plane = (uint32_t)a.N * (uint32_t)sizeof(S);
+    const uint32_t plane = (uint32_t)a.P * (uint32_t)sizeof(S);
     RowOffsets<S> o;
     bool active;
     if (!row_item<D, S, 32>(a, lane & 31, role ? plane : 0u, o, active)) return;
@@ -157,7 +157,7 @@ void k_step_split_lds(const StepArgs a) {
     const int role = lane >> 5;  // 0: g, 1: h
     const int c = wave * 32 + (lane & 31);  // the lane's cell in the tile
     const bool open_x = a.open_end & 1u, open_y = a.open_end & 2u, open_z = a.open_end & 4u;
-    const int64_t N = a.N;
+    const int64_t N = a.P;  // plane stride
     const S* src = static_cast<const S*>(a.src);
     // halo lanes (k = lane & 31 < 6): cells x0 - 3 .. x0 - 1, x0 + 128 .. x0 + 130
     const int hk = lane & 31;
@@ -240,7 +240,8 @@ template <int D, class P>
 __global__ __launch_bounds__(256) void k_init(char* dst, const double* __restrict__ rho_in,
                                               const double* __restrict__ u_in,
                                               const double* __restrict__ T_in, int64_t N,
-                                              double half_delta, double r, const WGroups wg) {
+                                              int64_t stride, double half_delta, double r,
+                                              const WGroups wg) {
     constexpr VelSet<D> V = kVelSet<D>;
     constexpr int Q = VelSet<D>::Q;
     const int64_t cell = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -254,7 +255,7 @@ __global__ __launch_bounds__(256) void k_init(char* dst, const double* __restric
     eq.setup(u, temp - 1.0, r);
     const double hdT = half_delta * temp;
     using S = typename P::S;
-    const size_t plane = (size_t)N * sizeof(S);
+    const size_t plane = (size_t)stride * sizeof(S);
     static_for<0, Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr Vel v = V.v[i];
@@ -319,7 +320,7 @@ void k_fd_step(const StepArgs a) {
     using S = typename P::S;
     constexpr int Q = VelSet<D>::Q;
     const int lane = (int)threadIdx.x & 63;
-    const uint32_t plane = (uint32_t)a.N * (uint32_t)sizeof(S);
+    const uint32_t plane = (uint32_t)a.P * (uint32_t)sizeof(S);
     const char* src = static_cast<const char*>(a.src);
     char* dst = static_cast<char*>(a.dst);
     RowOffsets<S> o;
@@ -359,7 +360,7 @@ __global__ __launch_bounds__(kReadBlock) void k_readout(const ReadArgs a) {
         pt.fill(x, y, z, a.nx, a.ny, a.nz, a.nxy, a.open_end, a.stream != 0);
         using S = typename P::S;
         constexpr bool DEV = P::kDev;
-        const uint32_t plane = (uint32_t)a.N * (uint32_t)sizeof(S);
+        const uint32_t plane = (uint32_t)a.P * (uint32_t)sizeof(S);
         const char* src = static_cast<const char*>(a.src);
         double s0 = 0, sj[3] = {0, 0, 0}, se = 0, sh = 0;
         static_for<0, Q>([&](auto I) {
@@ -492,8 +493,8 @@ hipError_t with_policy(int precision, F&& f) {
 }
 
 hipError_t launch_init(int dim, int precision, void* dst, const double* rho,
-                       const double* u, const double* T, int64_t N, double half_delta,
-                       double r, const double* w_group, hipStream_t s) {
+                       const double* u, const double* T, int64_t N, int64_t stride,
+                       double half_delta, double r, const double* w_group, hipStream_t s) {
     WGroups wg;
     for (int k = 0; k < 10; ++k) wg.w[k] = w_group[k];
     const int grid = (int)((N + 255) / 256);
@@ -501,8 +502,8 @@ hipError_t launch_init(int dim, int precision, void* dst, const double* rho,
     return with_policy(precision, [&](auto pol) {
         using P = decltype(pol);
         if (dim == 2)
-            return launch_kernel(&k_init<2, P>, dim3(grid), dim3(256), s, d, rho, u, T, N, half_delta, r, wg);
-        return launch_kernel(&k_init<3, P>, dim3(grid), dim3(256), s, d, rho, u, T, N, half_delta, r, wg);
+            return launch_kernel(&k_init<2, P>, dim3(grid), dim3(256), s, d, rho, u, T, N, stride, half_delta, r, wg);
+        return launch_kernel(&k_init<3, P>, dim3(grid), dim3(256), s, d, rho, u, T, N, stride, half_delta, r, wg);
     });
 }
 

@@ -168,6 +168,29 @@ Physics physics_of(int dim, double delta, double tau_f, double tau_g, double dt,
     return ph;
 }
 
+// Population planes of the benchmark grids (256^3, 4096^2) are a large power
+// of two bytes apart (a plane of 2^24 cells), and the 2Q plane streams of a
+// step then start at one offset modulo every power of two up to that size.
+// Moving the planes apart by a few kilobytes made the step faster on
+// average over repeated allocations (each measured 2-15 times; single
+// allocations vary by +-8% around these means): D3Q107 FP16 by 13%, FP32 by
+// 4%, D2Q37 FP32 by 5%, FP16 and FP64 by 2-3%; D3Q107 FP64 by under 1%.  The
+// pads are those means' best of the sizes tried.  Planes under 32 MiB
+// (every smaller grid, the bulk of a serving pool) are only rounded up to
+// 128 bytes, which keeps 16-byte row loads aligned.
+namespace {
+constexpr int64_t kPadFrom = int64_t(32) << 20;
+constexpr int64_t kPad3[3] = {8320, 16896, 1280};   // D3Q107: 2-, 4-, 8-byte values
+constexpr int64_t kPad2[3] = {33024, 16640, 8704};  // D2Q37
+}  // namespace
+
+int64_t plane_stride(int64_t N, size_t elem, int dim) {
+    const int64_t bytes = (N * (int64_t)elem + 127) / 128 * 128;
+    if (bytes < kPadFrom) return bytes / (int64_t)elem;
+    const int k = elem == 2 ? 0 : (elem == 4 ? 1 : 2);
+    return (bytes + (dim == 3 ? kPad3[k] : kPad2[k])) / (int64_t)elem;
+}
+
 const LatticeTables& lattice_tables(int dim) {
     std::call_once(g_once, [] {
         derive<2>(g_tables[0]);

@@ -48,9 +48,10 @@ struct Physics {
 // Arguments of the fused step kernel (passed by value in the kernarg
 // segment, so every field is wave-uniform and lives in SGPRs).
 struct StepArgs {
-    const void* src;      // [Q][2][N]: per population the g plane, then the h plane
+    const void* src;      // [Q][2][P]: per population the g plane, then the h plane
     void* dst;            // same layout
     int64_t N;            // cells
+    int64_t P;            // plane stride in cells (>= N; see plane_stride)
     int32_t nx, ny, nz;
     int32_t nxy;          // nx * ny
     uint32_t open_end;    // bit k: axis k is zero-gradient, else periodic
@@ -65,6 +66,11 @@ struct StepArgs {
     Physics ph;
 };
 
+// Plane stride (cells) of a solve's population planes for N cells of elem
+// bytes each in dim dimensions (lattice.cpp): N rounded up to 128 bytes, and
+// for large planes moved off a large power of two bytes apart.
+int64_t plane_stride(int64_t N, size_t elem, int dim);
+
 // Collision parameters of a solve (lattice.cpp).  dt > 0 selects the
 // finite-difference form: relaxation rates dt / tau, convection scale dt r / 6.
 // energy_fix selects the energy-conserving collision (see collide_*).
@@ -75,6 +81,7 @@ Physics physics_of(int dim, double delta, double tau_f, double tau_g, double dt 
 struct ReadArgs {
     const void* src;
     int64_t N;
+    int64_t P;                // plane stride of src in cells
     int32_t nx, ny, nz, nxy;
     uint32_t open_end;
     int32_t stream;           // 1: the source holds P_{n-1}; pull to get S_n
@@ -107,7 +114,7 @@ inline hipError_t launch_kernel(void (*kernel)(KArgs...), dim3 grid, dim3 block,
 // lane holds the g populations of a cell and its partner lane (lane ^ 32)
 // the h populations.
 hipError_t launch_init(int dim, int precision, void* dst, const double* rho,
-                       const double* u, const double* T, int64_t N,
+                       const double* u, const double* T, int64_t N, int64_t stride,
                        double half_delta, double r, const double* w_group,
                        hipStream_t s);
 // D3Q107 lattice step with the pulled rows staged in LDS (nx a multiple of
@@ -123,7 +130,7 @@ hipError_t launch_fd_step(int dim, int precision, bool split, const StepArgs& a,
 // record, then update passes over chunks of populations, which also leave
 // the next step's record behind (record_valid: skip the moments pass).
 // FP64 and FP32 deviation storage.
-size_t fd_record_bytes(int dim, int precision, int64_t N);
+size_t fd_record_bytes(int dim, int precision, int64_t P);
 hipError_t launch_fd_two_pass(int dim, int precision, const StepArgs& a, void* record,
                               bool record_valid, hipStream_t s);
 int step_block_cells(int dim, int precision, bool split);
@@ -146,11 +153,12 @@ int solver_readout(lbm_solver* h, double* rho, double* u, double* E, double* T, 
 struct lbm_solver {
     int dim, q, precision;
     int64_t nx, ny, nz, N;
+    int64_t P;            // plane stride in cells (lbm::plane_stride)
     uint32_t bc;
     double gamma, delta, tau_f, tau_g;
     const lbm::LatticeTables* lat;
     size_t elem;          // bytes per stored value
-    size_t buf_bytes;     // bytes of one ping-pong side (2 Q N elem)
+    size_t buf_bytes;     // bytes of one ping-pong side (2 Q P elem)
     void* buf[2];         // ping-pong sides
     int cur;              // side holding the latest post-collision state
     bool have_state;

@@ -42,7 +42,7 @@ namespace lbm {
 struct SolveEntry {
     uint64_t base;        // byte address of side 0 (side 1 follows)
     uint64_t side_bytes;
-    int32_t N, nx, ny, nz, nxy;
+    int32_t N, P, nx, ny, nz, nxy;  // P: plane stride in cells (plane_stride)
     uint32_t open_end;
     int32_t segs, rows, items, tiles_per_row, xcd_rows, tiles;
     int32_t dim, active;
@@ -122,7 +122,7 @@ void k_pool_step(const PoolArgs pa) {
     const int z = row / e.ny;
     const int xr = seg * L + (SPLIT ? (lane & 31) : lane);
     const int x = xr < e.nx ? xr : e.nx - 1;  // tail lanes redo the last cell
-    const uint32_t plane = (uint32_t)e.N * (uint32_t)sizeof(S);
+    const uint32_t plane = (uint32_t)e.P * (uint32_t)sizeof(S);
     RowOffsets<S> o;
     fill_row_offsets<D, S>(o, x, y, z, e.nx, e.ny, e.nz, e.nxy, e.open_end, true,
                            role ? plane : 0u);
@@ -187,7 +187,7 @@ hipError_t launch_pool_step(int precision, int dim, const PoolArgs& a, int grid,
 struct Slot {
     bool used = false;
     int dim = 0;
-    int64_t nx = 0, ny = 0, nz = 0, N = 0;
+    int64_t nx = 0, ny = 0, nz = 0, N = 0, P = 0;
     uint32_t bc = 0;
     double gamma = 0, delta = 0, tau_f = 0, tau_g = 0;
     int64_t steps_total = 0;
@@ -395,6 +395,7 @@ int pool_readout(lbm_pool* p, int slot, double* rho, double* u, double* E, doubl
     a.src = reinterpret_cast<const void*>(e.base + (side ? e.side_bytes : 0));
     a.stream = n == 0 ? 0 : 1;
     a.N = sl.N;
+    a.P = sl.P;
     a.nx = (int32_t)sl.nx;
     a.ny = (int32_t)sl.ny;
     a.nz = (int32_t)sl.nz;
@@ -508,6 +509,8 @@ static bool request_valid(const lbm_request* r, int precision, double* delta_out
     const double N = (double)r->nx * (double)r->ny * (double)r->nz;
     const size_t elem = precision == LBM_FP64 ? 8 : (precision == LBM_FP32_DEV ? 4 : 2);
     if (N * (double)elem > 2147483647.0) return false;
+    const int64_t P = lbm::plane_stride(r->nx * r->ny * r->nz, elem, r->dim);
+    if ((double)P * (double)elem > 2147483647.0) return false;
     if (!(r->gamma > 1.0) || !std::isfinite(r->gamma)) return false;
     double delta = 2.0 / (r->gamma - 1.0) - r->dim;
     if (std::fabs(delta) < 1e-9) delta = 0.0;
@@ -525,10 +528,10 @@ static bool request_valid(const lbm_request* r, int precision, double* delta_out
 
 size_t lbm_pool_request_bytes(const lbm_request* r, int precision) {
     if (!request_valid(r, precision, nullptr)) return 0;
-    const size_t N = (size_t)r->nx * (size_t)r->ny * (size_t)r->nz;
     const size_t elem = precision == LBM_FP64 ? 8 : (precision == LBM_FP32_DEV ? 4 : 2);
+    const size_t P = (size_t)lbm::plane_stride(r->nx * r->ny * r->nz, elem, r->dim);
     const int q = r->dim == 2 ? LBM_D2Q37 : LBM_D3Q107;
-    const size_t bytes = 2 * 2 * (size_t)q * N * elem;
+    const size_t bytes = 2 * 2 * (size_t)q * P * elem;
     return (bytes + 255) & ~(size_t)255;
 }
 
@@ -556,6 +559,8 @@ static int pool_admit(lbm_pool_handle p, const lbm_request* r, const double* rho
     sl.ny = r->ny;
     sl.nz = r->nz;
     sl.N = r->nx * r->ny * r->nz;
+    sl.P = lbm::plane_stride(sl.N, p->precision == LBM_FP64 ? 8 : (p->precision == LBM_FP32_DEV ? 4 : 2),
+                             r->dim);
     sl.bc = r->bc;
     sl.gamma = r->gamma;
     sl.delta = delta;
@@ -570,6 +575,7 @@ static int pool_admit(lbm_pool_handle p, const lbm_request* r, const double* rho
     e.base = reinterpret_cast<uint64_t>(p->arena + off);
     e.side_bytes = bytes / 2;
     e.N = (int32_t)sl.N;
+    e.P = (int32_t)sl.P;
     e.nx = (int32_t)r->nx;
     e.ny = (int32_t)r->ny;
     e.nz = (int32_t)r->nz;
@@ -625,7 +631,7 @@ static int pool_admit(lbm_pool_handle p, const lbm_request* r, const double* rho
     }
     char* side0 = p->arena + off;
     char* side1 = side0 + bytes / 2;
-    hipError_t e2 = lbm::launch_init(r->dim, p->precision, side1, drho, du, dT, sl.N,
+    hipError_t e2 = lbm::launch_init(r->dim, p->precision, side1, drho, du, dT, sl.N, sl.P,
                                      0.5 * delta, ph.r, ph.w, p->stream);
     if (e2 == hipSuccess) {
         lbm::StepArgs a;
@@ -633,6 +639,7 @@ static int pool_admit(lbm_pool_handle p, const lbm_request* r, const double* rho
         a.src = side1;
         a.dst = side0;
         a.N = sl.N;
+        a.P = sl.P;
         a.nx = e.nx;
         a.ny = e.ny;
         a.nz = e.nz;

@@ -37,7 +37,11 @@ class DevModel:
       "sequential"  sums over the populations one after the other,
       "perturbed"   pairwise, and after every collision each stored value
                     is moved by -1, 0 or +1 unit in the last place (seeded):
-                    a stand-in for any other rounding sequence.
+                    a stand-in for any other rounding sequence;
+      "widesum"     sequential, with the sums of the targets accumulated in
+                    float64 and rounded once;
+      "nofold"      sequential, without the exact-moment fold (the targets
+                    as the equilibrium gives them).
     ``dt``: None for lattice streaming, else the time step of the
     finite-difference form of Sec. III (grid step 1, speeds r e_i, rates
     dt/tau): forward Euler with the third-order upwind-biased convection per
@@ -123,7 +127,7 @@ class DevModel:
         """Sum over the populations (axis 1), optionally weighted."""
         if weights is not None:
             a = a * weights
-        if self.order == "sequential":
+        if self.order in ("sequential", "widesum", "nofold"):
             acc = np.zeros(a.shape[0], dtype=a.dtype)
             for i in range(a.shape[1]):
                 acc = acc + a[:, i]
@@ -161,8 +165,20 @@ class DevModel:
                 (h, hdT * rho, hdT * drho + hd * t, self.om_g, hd * (drho + rho * t), False)):
             tgt = self.w * (arho[:, None] * pm1 + beta[:, None])
             # fold the float residuals of the target moments back in
-            dm = want_m - self._sum(tgt)
-            if je:
+            if self.order == "widesum":
+                wide = tgt.astype(np.float64)
+                dm = want_m - np.sum(wide, axis=1).astype(T)
+            else:
+                dm = want_m - self._sum(tgt)
+            if self.order == "nofold":
+                dm = dm * T(0)
+            if je and self.order == "nofold":
+                de = dm
+                dj = np.zeros_like(sj)
+            elif je and self.order == "widesum":
+                de = want_e - (wide @ self.qn.astype(np.float64)).astype(T)
+                dj = sj - (wide @ self.e.astype(np.float64)).astype(T)
+            elif je:
                 de = want_e - self._sum(tgt, self.qf)
                 dj = sj - self._vsum(tgt)
                 tgt[:, self.rest] += dm - de

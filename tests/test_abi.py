@@ -145,6 +145,12 @@ def test_hbm_probe_library_exports_and_checks_arguments():
     assert lib.hbm_probe_copy(vp(4096 + 512), vp(4096), 1024, 0, None) == -1  # overlap
     assert lib.hbm_probe_copy(vp(8192), vp(4096), 1024, nv, None) == -1   # no such variant
     assert lib.hbm_probe_read(vp(4096), 1024, 0, None, None) == -1
+    lib.hbm_probe_planes.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int64, i32, vp]
+    big = 1 << 40  # far apart: only the shape checks below can fail
+    assert lib.hbm_probe_planes(vp(big), vp(4096), 256 * 4, 256 * 4, 100, None) == -1  # nx % 128
+    assert lib.hbm_probe_planes(vp(big), vp(4096), 256 * 4 + 5, 256 * 4 + 5, 256, None) == -1
+    assert lib.hbm_probe_planes(vp(big), vp(4096), 256 * 4, 256, 256, None) == -1  # stride < cells
+    assert lib.hbm_probe_planes(vp(4096 + 64), vp(4096), 256 * 4, 256 * 4, 256, None) == -1
 
 
 def test_pool_request_bytes_is_zero_for_any_invalid_request():

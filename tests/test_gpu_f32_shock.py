@@ -1,11 +1,11 @@
 """Shock tubes in FP32 deviation storage and FP64 on the GPU, against the
 oracle and against the float model of the same step (f32_model.py), with
-the bars of shock_cases.py: each a few times the largest difference that
+the bars of shock_cases.py: each 3-4 times the largest difference that
 correct evaluations of the step in the same floating-point type show
 against the oracle on that case (the CPU test test_f32_model.py measures
 them).  The GPU is one more such evaluation, with fused multiply-adds and
-its own summation order, so its difference to the oracle must fall inside
-that family's range, and so must its difference to one model evaluation.
+its own summation order; its difference to the oracle, and to one model
+evaluation, must stay within the bar.
 """
 import numpy as np
 import pytest

@@ -15,6 +15,7 @@ import pytest
 
 from paper_1608_06345_amd import lbm, serving
 from parity_util import oracle_run
+from shock_cases import FP32_BAR
 
 pytestmark = pytest.mark.gpu
 
@@ -165,4 +166,5 @@ def test_tube_parity_with_oracle():
         e_u = np.max(np.abs(u - o[1]))
         e_T = np.max(np.abs(T - o[2]) / o[2])
         print(f"tube {r.rid} FP32 vs oracle: rho {e_rho:.2e} u(abs) {e_u:.2e} T {e_T:.2e}")
-        assert max(e_rho, e_u, e_T) < 2e-3
+        # the shock-tube bar of this tube (shock_cases.py, float-model evidence)
+        assert max(e_rho, e_u, e_T) < FP32_BAR[f"tube{r.rid}"]
