@@ -268,8 +268,9 @@ int create_solver(int dim, int velocity_set, double gamma, double tau_f, double 
     h->buf_bytes = 2 * (size_t)s.q * (size_t)s.P * s.elem;
     h->read_blocks = read_blocks_of(s.N);
     // one lane per cell keeps all 2Q populations in registers; for D3Q107
-    // that is 214 values, so the 3D kernels split g and h across lane pairs
-    h->split = dim == 3;
+    // in float or double that is 214 values, so those kernels split g and h
+    // across lane pairs (half storage holds them as 107 g/h words)
+    h->split = lbm::default_split(dim, precision);
     h->lds = false;
     h->fd_fused = fd_fused_by_default(dim, precision, nx);
     hipError_t e = hipGetDevice(&h->device);
@@ -328,7 +329,7 @@ int lbm_set_variant(lbm_handle h, int variant) {
     if (!h) return LBM_EINVAL;
     switch (variant) {
         case LBM_VARIANT_AUTO:
-            h->split = h->dim == 3;
+            h->split = lbm::default_split(h->dim, h->precision);
             h->fd_fused = fd_fused_by_default(h->dim, h->precision, h->nx);
             h->lds = false;
             return LBM_OK;

@@ -84,16 +84,14 @@ void k_step(const StepArgs a) {
     bool active;
     if (!row_item<D, S, 64>(a, (int)threadIdx.x & 63, 0u, o, active)) return;
     const uint32_t plane = (uint32_t)a.P * (uint32_t)sizeof(S);
-    T g[Q], h[Q];
-    load_lane<D, P>(static_cast<const char*>(a.src), plane, o, g, h, a.ph);
-    collide_lane<D, P>(g, h, a.ph);
     // Lanes past the end of a ragged row hold the row's last cell (clamped),
     // loaded and updated exactly like the lane that owns it, so they store
     // the same bits to the same place.  No branch: a branch here lets the
     // compiler sink the whole relaxation into the store block and keep every
     // target and population live at once.
     (void)active;
-    store_lane<D, P>(static_cast<char*>(a.dst), plane, o, g, h, a.ph);
+    step_lane_cell<D, P>(static_cast<const char*>(a.src), static_cast<char*>(a.dst), plane, o,
+                         a.ph);
 }
 
 // Fused step, split layout (see collide_split): a wave serves 32 cells of
@@ -109,7 +107,8 @@ void k_step_split(const StepArgs a) {
     const uint32_t plane = (uint32_t)a.P * (uint32_t)sizeof(S);
     RowOffsets<S> o;
     bool active;
-    if (!row_item<D, S, 32>(a, lane & 31, role ? plane : 0u, o, active)) return;
+    if (!row_item<D, S, 32>(a, lane & 31, role ? h_offset(sizeof(S), plane) : 0u, o, active))
+        return;
     T p[Q];
     load_split<D, P>(static_cast<const char*>(a.src), plane, o, p, a.ph);
     collide_split<D, P>(p, role, a.ph);
@@ -140,6 +139,10 @@ void k_step_split_lds(const StepArgs a) {
     using T = typename P::T;
     using S = typename P::S;
     typedef S S4 __attribute__((ext_vector_type(4)));
+    typedef S S8 __attribute__((ext_vector_type(8)));
+    // half storage: g/h words, two elements per cell (see cell_bytes)
+    constexpr bool kPaired = sizeof(S) == 2;
+    constexpr int64_t kCellElems = kPaired ? 2 : 1;
     constexpr VelSet<D> V = kVelSet<D>;
     constexpr int Q = VelSet<D>::Q;
     __shared__ __attribute__((aligned(16))) S lds[kLdsBatch * 2 * kLdsRow];
@@ -180,8 +183,8 @@ void k_step_split_lds(const StepArgs a) {
                     constexpr Vel v = V.v[i];
                     const int64_t st =
                         (int64_t)(2 * i) * N +
-                        (int64_t)pull_coord(y, v.y, a.ny, open_y) * a.nx +
-                        (int64_t)pull_coord(z, v.z, a.nz, open_z) * a.nxy;
+                        kCellElems * ((int64_t)pull_coord(y, v.y, a.ny, open_y) * a.nx +
+                                      (int64_t)pull_coord(z, v.z, a.nz, open_z) * a.nxy);
                     const bool w = wave == decltype(W)::value;
                     start = w ? st : start;
                     has = w ? true : has;
@@ -190,9 +193,18 @@ void k_step_split_lds(const StepArgs a) {
             });
             hv[m] = S(0);
             if (has) {
-                const S* rowp = src + start + (role ? N : 0);
-                q[m] = *reinterpret_cast<const S4*>(rowp + x0 + 4 * (lane & 31));
-                if (hx_need && hk < 6) hv[m] = rowp[hx];
+                if constexpr (kPaired) {
+                    // four cells' g/h words (16 bytes); keep this lane's halves
+                    const S* rowp = src + start;
+                    const S8 pw = *reinterpret_cast<const S8*>(rowp + 2 * (x0 + 4 * (lane & 31)));
+                    q[m] = role ? __builtin_shufflevector(pw, pw, 1, 3, 5, 7)
+                                : __builtin_shufflevector(pw, pw, 0, 2, 4, 6);
+                    if (hx_need && hk < 6) hv[m] = rowp[2 * hx + role];
+                } else {
+                    const S* rowp = src + start + (role ? N : 0);
+                    q[m] = *reinterpret_cast<const S4*>(rowp + x0 + 4 * (lane & 31));
+                    if (hx_need && hk < 6) hv[m] = rowp[hx];
+                }
             }
         });
     };
@@ -227,8 +239,8 @@ void k_step_split_lds(const StepArgs a) {
     collide_split<D, P>(p, role, a.ph);
     const uint32_t plane = (uint32_t)N * (uint32_t)sizeof(S);
     RowOffsets<S> o;
-    o.row = (uint32_t)(y * a.nx + z * a.nxy) * (uint32_t)sizeof(S);
-    o.own = (uint32_t)(x0 + c) * (uint32_t)sizeof(S) + (role ? plane : 0u);
+    o.row = (uint32_t)(y * a.nx + z * a.nxy) * cell_bytes(sizeof(S));
+    o.own = (uint32_t)(x0 + c) * cell_bytes(sizeof(S)) + (role ? h_offset(sizeof(S), plane) : 0u);
     store_split<D, P>(static_cast<char*>(a.dst), plane, o, p, a.ph);
 }
 
@@ -280,8 +292,9 @@ __global__ __launch_bounds__(256) void k_init(char* dst, const double* __restric
         }
         // rounded once, from double, to the storage type (via float for half)
         using Mid = std::conditional_t<sizeof(S) < 4, float, S>;
-        reinterpret_cast<S*>(base)[cell] = S(Mid(gv));
-        reinterpret_cast<S*>(base + plane)[cell] = S(Mid(hv));
+        char* at = base + (size_t)cell * cell_bytes(sizeof(S));
+        *reinterpret_cast<S*>(at) = S(Mid(gv));
+        *reinterpret_cast<S*>(at + h_offset(sizeof(S), (uint32_t)plane)) = S(Mid(hv));
     });
 }
 
@@ -326,7 +339,7 @@ void k_fd_step(const StepArgs a) {
     RowOffsets<S> o;
     if constexpr (SPLIT) {
         const int role = lane >> 5;  // 0: g, 1: h (see collide_split)
-        if (!fd_item<D, S, 32>(a, lane & 31, role ? plane : 0u, o)) return;
+        if (!fd_item<D, S, 32>(a, lane & 31, role ? h_offset(sizeof(S), plane) : 0u, o)) return;
         T p[Q];
         load_split<D, P, false>(src, plane, o, p, a.ph);
         collide_split<D, P, true>(p, role, a.ph);
@@ -366,11 +379,12 @@ __global__ __launch_bounds__(kReadBlock) void k_readout(const ReadArgs a) {
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             constexpr Vel v = V.v[i];
-            const uint32_t off = (uint32_t)pt.template src<v.x, v.y, v.z>() * (uint32_t)sizeof(S);
+            const uint32_t off =
+                (uint32_t)pt.template src<v.x, v.y, v.z>() * cell_bytes(sizeof(S));
             const char* base = src + (size_t)(2 * i) * plane;
             const double scale = P::kScaled ? a.w[v.group] : 1.0;
             const double gv = (double)load_at<S>(base, off) * scale;
-            const double hv = (double)load_at<S>(base, off + plane) * scale;
+            const double hv = (double)load_at<S>(base, off + h_offset(sizeof(S), plane)) * scale;
             s0 += gv;
             if constexpr (v.x != 0) sj[0] += double(v.x) * gv;
             if constexpr (v.y != 0) sj[1] += double(v.y) * gv;
@@ -457,15 +471,17 @@ hipError_t step_impl(bool split, const StepArgs& a0, hipStream_t s) {
     // whole rows per XCD once there are enough rows to keep all eight busy
     a.xcd_rows = a.rows >= 64 ? 1 : 0;
     const int grid = a.xcd_rows ? 8 * a.tiles_per_row * ((a.rows + 7) / 8) : (a.items + 3) / 4;
-    // Occupancy hint for the split D3Q107 float kernels: asking for at least
-    // two waves per SIMD gave 4% more bandwidth than the compiler's own
-    // choice (three waves at 162 VGPRs); the other kernels run best as
-    // compiled.
-    constexpr int kSplitWaves = (D == 3 && sizeof(typename P::T) == 4) ? 2 : 1;
+    // Occupancy hint for the split D3Q107 kernels, at least two waves per
+    // SIMD.  Float: 4% more bandwidth than the compiler's own choice (three
+    // waves at 162 VGPRs).  Double: the compiler's choice is one wave (256
+    // VGPRs + 28 AGPRs); two waves spill 30 values to scratch and still ran
+    // 2.4% faster (10.66 against 10.92 ms at 256^3, six interleaved fresh
+    // allocations each).  The other kernels run best as compiled.
+    constexpr int kSplitWaves = D == 3 ? 2 : 1;
     if (split)
         return launch_kernel(&k_step_split<D, P, kSplitWaves>, dim3(grid), dim3(256), s, a);
     else
-        return launch_kernel(&k_step<D, P, 1>, dim3(grid), dim3(256), s, a);
+        return launch_kernel(&k_step<D, P, P::kScaled ? 3 : 1>, dim3(grid), dim3(256), s, a);
 }
 
 template <int D, class P>
@@ -530,10 +546,11 @@ hipError_t launch_step(int dim, int precision, bool split, const StepArgs& a, hi
 int step_block_cells(int, int, bool split) { return split ? 128 : 256; }
 
 hipError_t launch_fd_step(int dim, int precision, bool split, const StepArgs& a, hipStream_t s) {
-    return with_policy(precision, [&](auto pol) {
-        using P = decltype(pol);
-        return dim == 2 ? fd_step_impl<2, P>(split, a, s) : fd_step_impl<3, P>(split, a, s);
-    });
+    // no half storage in the finite-difference form (lbm_create_fd refuses it)
+    if (precision == LBM_FP16_SCALED) return hipErrorInvalidValue;
+    if (precision == LBM_FP64)
+        return dim == 2 ? fd_step_impl<2, F64>(split, a, s) : fd_step_impl<3, F64>(split, a, s);
+    return dim == 2 ? fd_step_impl<2, F32Dev>(split, a, s) : fd_step_impl<3, F32Dev>(split, a, s);
 }
 
 hipError_t launch_readout(int dim, int precision, const ReadArgs& a, int blocks, hipStream_t s) {

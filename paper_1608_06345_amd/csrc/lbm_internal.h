@@ -71,6 +71,25 @@ struct StepArgs {
 // for large planes moved off a large power of two bytes apart.
 int64_t plane_stride(int64_t N, size_t elem, int dim);
 
+// Storage layout of one ping-pong side.  Population i owns the slab of
+// 2 P elem bytes that starts at byte 2 i P elem.  In FP64 and FP32 the slab
+// holds the g plane and then the h plane.  In half storage the g and h
+// values of a cell share one 32-bit word, g in the low half, so that one
+// 4-byte access moves both populations of the cell.  cell_bytes: distance
+// from one cell to the next; h_offset: where h sits relative to g.
+constexpr uint32_t cell_bytes(size_t elem) { return elem == 2 ? 4u : (uint32_t)elem; }
+constexpr uint32_t h_offset(size_t elem, uint32_t plane_bytes) {
+    return elem == 2 ? 2u : plane_bytes;
+}
+
+// Register layout the lattice step takes by default.  D3Q107 in float or
+// double splits g and h over lane pairs (214 values do not fit one lane);
+// half storage keeps one cell per lane in both velocity sets, its 214 halves
+// held as 107 g/h words.
+constexpr bool default_split(int dim, int precision) {
+    return dim == 3 && precision != LBM_FP16_SCALED;
+}
+
 // Collision parameters of a solve (lattice.cpp).  dt > 0 selects the
 // finite-difference form: relaxation rates dt / tau, convection scale dt r / 6.
 // energy_fix selects the energy-conserving collision (see collide_*).

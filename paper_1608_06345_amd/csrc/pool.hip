@@ -125,7 +125,7 @@ void k_pool_step(const PoolArgs pa) {
     const uint32_t plane = (uint32_t)e.P * (uint32_t)sizeof(S);
     RowOffsets<S> o;
     fill_row_offsets<D, S>(o, x, y, z, e.nx, e.ny, e.nz, e.nxy, e.open_end, true,
-                           role ? plane : 0u);
+                           role ? h_offset(sizeof(S), plane) : 0u);
     const int par = (int)(done & 1);
     const char* src = reinterpret_cast<const char*>(e.base + (par ? e.side_bytes : 0));
     char* dst = reinterpret_cast<char*>(e.base + (par ? 0 : e.side_bytes));
@@ -140,10 +140,7 @@ void k_pool_step(const PoolArgs pa) {
         collide_split<D, P>(p, role, ph);
         store_split<D, P>(dst, plane, o, p, ph);
     } else {
-        T g[Q], h[Q];
-        load_lane<D, P>(src, plane, o, g, h, ph);
-        collide_lane<D, P>(g, h, ph);
-        store_lane<D, P>(dst, plane, o, g, h, ph);
+        step_lane_cell<D, P>(src, dst, plane, o, ph);
     }
 }
 
@@ -156,13 +153,18 @@ __global__ __launch_bounds__(256) void k_advance(const SolveEntry* table, int64_
 }
 
 // The step kernel of a velocity set, in the pool's precision: the same
-// layouts as the single-solve launches (one lane per cell for D2Q37, the g/h
-// lane-pair split for D3Q107).
+// layouts as the single-solve launches (default_split: one lane per cell for
+// D2Q37 and for half storage, the g/h lane-pair split for D3Q107 in float
+// and double).
 template <class P>
 const void* pool_step_kernel_p(int dim) {
     if (dim == 2) return reinterpret_cast<const void*>(&k_pool_step<2, P, false, 1>);
-    constexpr int w = sizeof(typename P::T) == 4 ? 2 : 1;
-    return reinterpret_cast<const void*>(&k_pool_step<3, P, true, w>);
+    if constexpr (P::kScaled) {
+        return reinterpret_cast<const void*>(&k_pool_step<3, P, false, 1>);
+    } else {
+        constexpr int w = sizeof(typename P::T) == 4 ? 2 : 1;
+        return reinterpret_cast<const void*>(&k_pool_step<3, P, true, w>);
+    }
 }
 
 const void* pool_step_kernel(int precision, int dim) {
@@ -174,8 +176,12 @@ const void* pool_step_kernel(int precision, int dim) {
 template <class P>
 hipError_t launch_pool_step_p(int dim, const PoolArgs& a, int grid, hipStream_t s) {
     if (dim == 2) return launch_kernel(&k_pool_step<2, P, false, 1>, dim3(grid), dim3(256), s, a);
-    constexpr int w = sizeof(typename P::T) == 4 ? 2 : 1;
-    return launch_kernel(&k_pool_step<3, P, true, w>, dim3(grid), dim3(256), s, a);
+    if constexpr (P::kScaled) {
+        return launch_kernel(&k_pool_step<3, P, false, 1>, dim3(grid), dim3(256), s, a);
+    } else {
+        constexpr int w = sizeof(typename P::T) == 4 ? 2 : 1;
+        return launch_kernel(&k_pool_step<3, P, true, w>, dim3(grid), dim3(256), s, a);
+    }
 }
 
 hipError_t launch_pool_step(int precision, int dim, const PoolArgs& a, int grid, hipStream_t s) {
@@ -290,8 +296,8 @@ void arena_free(lbm_pool* p, size_t off, size_t bytes) {
     }
 }
 
-int tiles_of(int dim, int64_t nx, int64_t ny, int64_t nz, SolveEntry& e) {
-    const int L = dim == 3 ? 32 : 64;  // split layout in 3D, one lane per cell in 2D
+int tiles_of(int dim, int precision, int64_t nx, int64_t ny, int64_t nz, SolveEntry& e) {
+    const int L = lbm::default_split(dim, precision) ? 32 : 64;  // cells per wave
     e.segs = (int)((nx + L - 1) / L);
     e.rows = (int)(ny * nz);
     e.items = e.segs * e.rows;
@@ -581,7 +587,7 @@ static int pool_admit(lbm_pool_handle p, const lbm_request* r, const double* rho
     e.nz = (int32_t)r->nz;
     e.nxy = (int32_t)(r->nx * r->ny);
     e.open_end = (r->bc & 3u) | (((r->bc >> 2) & 3u) << 1) | (((r->bc >> 4) & 3u) << 2);
-    e.tiles = tiles_of(r->dim, r->nx, r->ny, r->nz, e);
+    e.tiles = tiles_of(r->dim, p->precision, r->nx, r->ny, r->nz, e);
     e.dim = r->dim;
     e.active = 1;
     e.steps_total = r->steps;
@@ -647,7 +653,8 @@ static int pool_admit(lbm_pool_handle p, const lbm_request* r, const double* rho
         a.open_end = e.open_end;
         a.stream = 0;
         a.ph = ph;
-        e2 = lbm::launch_step(r->dim, p->precision, r->dim == 3, a, p->stream);
+        e2 = lbm::launch_step(r->dim, p->precision, lbm::default_split(r->dim, p->precision), a,
+                              p->stream);
     }
     if (e2 == hipSuccess) {
         p->h_steps[slot] = 0;

@@ -151,15 +151,28 @@ __device__ __forceinline__ T fmadd(T a, T b, T c) {
 // unrounded target, and the correction would then not cancel the rounding
 // of the targets it is applied to (measured: 10x the float32 error on a
 // shock tube).
+// Even and odd parts of P(c): P(+-c) = even +- odd.
+template <typename T>
+__device__ __forceinline__ void pair_parts(T A0, T A1, T A2, T c, T& even, T& odd) {
+#pragma clang fp contract(off)
+    const T c2 = c * c;
+    even = fmadd(c2, fmadd(c2, T(1.0 / 24.0), A2), A0);
+    odd = c * fmadd(c2, T(1.0 / 6.0), A1);
+}
+
+template <typename T>
+__device__ __forceinline__ void pair_finish(T even, T odd, T w, T arho, T beta, T& tp, T& tm) {
+#pragma clang fp contract(off)
+    tp = w * fmadd(arho, even + odd, beta);
+    tm = w * fmadd(arho, even - odd, beta);
+}
+
 template <typename T>
 __device__ __forceinline__ void pair_targets(T A0, T A1, T A2, T c, T w, T arho, T beta, T& tp,
                                              T& tm) {
-#pragma clang fp contract(off)
-    const T c2 = c * c;
-    const T even = fmadd(c2, fmadd(c2, T(1.0 / 24.0), A2), A0);
-    const T odd = c * fmadd(c2, T(1.0 / 6.0), A1);
-    tp = w * fmadd(arho, even + odd, beta);
-    tm = w * fmadd(arho, even - odd, beta);
+    T even, odd;
+    pair_parts(A0, A1, A2, c, even, odd);
+    pair_finish(even, odd, w, arho, beta, tp, tm);
 }
 
 // Target of the rest population (c = 0), rounded once as above.
@@ -223,15 +236,15 @@ struct F16Dev {
 
 // Moment sums over one set of Q populations p (scaled lattice units):
 // s0 = sum p, sj = sum e p, se = sum |e|^2 p.
-template <int D, typename T>
-__device__ __forceinline__ void moment_sums(const T* p, T& s0, T* sj, T& se) {
+template <int D, typename T, class Get>
+__device__ __forceinline__ void moment_sums_of(Get&& get, T& s0, T* sj, T& se) {
     constexpr VelSet<D> V = kVelSet<D>;
     constexpr int Q = VelSet<D>::Q;
     T a0 = 0, ax = 0, ay = 0, az = 0, ae = 0;
     static_for<0, Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr Vel v = V.v[i];
-        const T x = p[i];
+        const T x = get(I);
         a0 += x;
         if constexpr (v.x != 0) ax += T(v.x) * x;
         if constexpr (v.y != 0) ay += T(v.y) * x;
@@ -243,6 +256,11 @@ __device__ __forceinline__ void moment_sums(const T* p, T& s0, T* sj, T& se) {
     sj[1] = ay;
     if constexpr (D == 3) sj[2] = az;
     se = ae;
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void moment_sums(const T* p, T& s0, T* sj, T& se) {
+    moment_sums_of<D, T>([&](auto I) { return p[decltype(I)::value]; }, s0, sj, se);
 }
 
 // |e|_1 of a lattice vector.
@@ -291,27 +309,45 @@ __device__ __forceinline__ float fd_scale<float>(const Physics& ph) { return ph.
 // population also loses the centre term of its upwind-biased convection,
 // 3 |e_i|_1 (dt r / 6) p_i, taken from the pre-collision value; the
 // neighbour terms are added by convect_store_* below.
-template <int D, typename T, bool DEV, bool FD = false>
-__device__ __forceinline__ void relax(T* p, const Equilibrium<D, T, DEV>& eq,
-                                      const Physics& a, T arho, T beta, T omega, T want_m,
-                                      const T* want_j, T want_e, T je_on) {
+// Relaxation parameters of one distribution (see relax).
+template <typename T>
+struct RelaxPar {
+    T arho, beta, omega, want_m, want_e, je_on;
+};
+
+// relax for K distributions of one cell at once (K = 2: g and h of a lane
+// that holds both): each pair's polynomial is formed once and serves every
+// distribution.  Per distribution the arithmetic, and the order of every
+// sum, is that of K = 1.  p.get<k, i>() / p.set<k, i>(v): population i of
+// distribution k.
+template <int D, typename T, bool DEV, bool FD, int K, class Acc>
+__device__ __forceinline__ void relax_k(const Acc& p, const Equilibrium<D, T, DEV>& eq,
+                                        const Physics& a, const RelaxPar<T>* r,
+                                        const T* want_j) {
 #pragma clang fp contract(off)
     constexpr VelSet<D> V = kVelSet<D>;
     constexpr int G = VelSet<D>::G;
     // p + omega (t - p), less the convection centre term in FD
-    auto update = [&](T& pi, T t, auto L1) {
+    auto update = [&](auto Kc, auto Ic, T t, auto L1) {
+        constexpr int k = decltype(Kc)::value;
+        constexpr int i = decltype(Ic)::value;
         constexpr int l1 = decltype(L1)::value;
+        const T pi = p.template get<k, i>();
         if constexpr (FD && l1 != 0) {
             const T kc = T(3 * l1) * fd_scale<T>(a);
-            pi = relax_value(pi, t, omega, kc);
+            p.template set<k, i>(relax_value(pi, t, r[k].omega, kc));
         } else {
-            pi = relax_value(pi, t, omega);
+            p.template set<k, i>(relax_value(pi, t, r[k].omega));
         }
     };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
     static_assert(V.v[1].group == 1 && V.v[2 * D].group == 1 && V.v[2 * D + 1].group == 2,
                   "the axis populations must follow the rest population");
-    T sm = 0, sjx = 0, sjy = 0, sjz = 0, se = 0;
-    T t1[2 * D];  // targets of the axis populations, corrected below
+    T sm[K], sjx[K], sjy[K], sjz[K], se[K];
+    T t1[K][2 * D];  // targets of the axis populations, corrected below
+#pragma unroll
+    for (int k = 0; k < K; ++k) sm[k] = sjx[k] = sjy[k] = sjz[k] = se[k] = T(0);
     static_for<1, G>([&](auto Gi) {
         constexpr int g = decltype(Gi)::value;
         T A0, A1, A2;
@@ -322,49 +358,89 @@ __device__ __forceinline__ void relax(T* p, const Equilibrium<D, T, DEV>& eq,
             constexpr int i = first + 2 * decltype(Pi)::value;
             constexpr Vel v = V.v[i];
             const T c = eq.template dot<v.x, v.y, v.z>();
-            T tp, tm;
-            pair_targets(A0, A1, A2, c, w, arho, beta, tp, tm);
-            if constexpr (DEV) {
-                const T sum = tp + tm;
-                const T dif = tp - tm;
-                sm += sum;
-                if constexpr (v.x != 0) sjx = fmadd(T(v.x), dif, sjx);
-                if constexpr (v.y != 0) sjy = fmadd(T(v.y), dif, sjy);
-                if constexpr (D == 3 && v.z != 0) sjz = fmadd(T(v.z), dif, sjz);
-                se = fmadd(T(V.qn[g]), sum, se);
-            }
-            if constexpr (DEV && g == 1) {
-                t1[i - 1] = tp;
-                t1[i] = tm;
-            } else {
-                update(p[i], tp, std::integral_constant<int, l1_of(v)>{});
-                update(p[i + 1], tm, std::integral_constant<int, l1_of(v)>{});
-            }
+            T even, odd;
+            pair_parts(A0, A1, A2, c, even, odd);
+            static_for<0, K>([&](auto Kc) {
+                constexpr int k = decltype(Kc)::value;
+                T tp, tm;
+                pair_finish(even, odd, w, r[k].arho, r[k].beta, tp, tm);
+                if constexpr (DEV) {
+                    const T sum = tp + tm;
+                    const T dif = tp - tm;
+                    sm[k] += sum;
+                    if constexpr (v.x != 0) sjx[k] = fmadd(T(v.x), dif, sjx[k]);
+                    if constexpr (v.y != 0) sjy[k] = fmadd(T(v.y), dif, sjy[k]);
+                    if constexpr (D == 3 && v.z != 0) sjz[k] = fmadd(T(v.z), dif, sjz[k]);
+                    se[k] = fmadd(T(V.qn[g]), sum, se[k]);
+                }
+                if constexpr (DEV && g == 1) {
+                    t1[k][i - 1] = tp;
+                    t1[k][i] = tm;
+                } else {
+                    update(Kc, std::integral_constant<int, i>{}, tp,
+                           std::integral_constant<int, l1_of(v)>{});
+                    update(Kc, std::integral_constant<int, i + 1>{}, tm,
+                           std::integral_constant<int, l1_of(v)>{});
+                }
+            });
         });
     });
     T A0, A1, A2;
     eq.template coef<0>(A0, A1, A2);
-    T t0 = rest_target(A0, weight<T>(a, 0), arho, beta);
-    if constexpr (DEV) {
-        sm += t0;
-        const T dm = want_m - sm;
-        const T de = je_on * (want_e - se);
-        const T dj[3] = {je_on * (want_j[0] - sjx), je_on * (want_j[1] - sjy),
-                         D == 3 ? je_on * (want_j[2] - sjz) : T(0)};
-        t0 += dm - de;
-        const T de_axis = de * T(1.0 / (2 * D));
-        static_for<0, D>([&](auto I) {
-            constexpr int k = decltype(I)::value;
-            constexpr Vel v = V.v[1 + 2 * k];  // +e_axis (first of its pair)
-            constexpr int axis = v.x != 0 ? 0 : (v.y != 0 ? 1 : 2);
-            const T half = T(0.5) * dj[axis];
-            const T tp = t1[2 * k] + de_axis + half;
-            const T tm = t1[2 * k + 1] + de_axis - half;
-            update(p[1 + 2 * k], tp, std::integral_constant<int, 1>{});
-            update(p[2 + 2 * k], tm, std::integral_constant<int, 1>{});
-        });
-    }
-    update(p[0], t0, std::integral_constant<int, 0>{});
+    static_for<0, K>([&](auto Kc) {
+        constexpr int k = decltype(Kc)::value;
+        T t0 = rest_target(A0, weight<T>(a, 0), r[k].arho, r[k].beta);
+        if constexpr (DEV) {
+            sm[k] += t0;
+            const T je_on = r[k].je_on;
+            const T dm = r[k].want_m - sm[k];
+            const T de = je_on * (r[k].want_e - se[k]);
+            const T dj[3] = {je_on * (want_j[0] - sjx[k]), je_on * (want_j[1] - sjy[k]),
+                             D == 3 ? je_on * (want_j[2] - sjz[k]) : T(0)};
+            t0 += dm - de;
+            const T de_axis = de * T(1.0 / (2 * D));
+            static_for<0, D>([&](auto I) {
+                constexpr int q = decltype(I)::value;
+                constexpr Vel v = V.v[1 + 2 * q];  // +e_axis (first of its pair)
+                constexpr int axis = v.x != 0 ? 0 : (v.y != 0 ? 1 : 2);
+                const T half = T(0.5) * dj[axis];
+                const T tp = t1[k][2 * q] + de_axis + half;
+                const T tm = t1[k][2 * q + 1] + de_axis - half;
+                update(Kc, std::integral_constant<int, 1 + 2 * q>{}, tp, I1{});
+                update(Kc, std::integral_constant<int, 2 + 2 * q>{}, tm, I1{});
+            });
+        }
+        update(Kc, I0{}, t0, I0{});
+    });
+}
+
+// One distribution held in an array.
+template <typename T>
+struct ArrayAcc1 {
+    T* p;
+    template <int K, int I>
+    __device__ __forceinline__ T get() const { return p[I]; }
+    template <int K, int I>
+    __device__ __forceinline__ void set(T v) const { p[I] = v; }
+};
+
+// Distribution K0 of a two-distribution accessor, as a one-distribution one.
+template <int K0, class Acc>
+struct Slice {
+    const Acc& p;
+    template <int K, int I>
+    __device__ __forceinline__ auto get() const { return p.template get<K0, I>(); }
+    template <int K, int I, typename V>
+    __device__ __forceinline__ void set(V v) const { p.template set<K0, I>(v); }
+};
+
+// The BGK relaxation of one distribution (the parameters as in RelaxPar).
+template <int D, typename T, bool DEV, bool FD = false>
+__device__ __forceinline__ void relax(T* p, const Equilibrium<D, T, DEV>& eq,
+                                      const Physics& a, T arho, T beta, T omega, T want_m,
+                                      const T* want_j, T want_e, T je_on) {
+    const RelaxPar<T> r{arho, beta, omega, want_m, want_e, je_on};
+    relax_k<D, T, DEV, FD, 1>(ArrayAcc1<T>{p}, eq, a, &r, want_j);
 }
 
 // Macroscopic state of a cell from the moment sums.
@@ -417,18 +493,19 @@ template <int D, typename T>
 __device__ __forceinline__ void fill_row_offsets(RowOffsets<T>& o, int x, int y, int z, int nx,
                                                  int ny, int nz, int nxy, uint32_t open_end,
                                                  bool stream, uint32_t role_off) {
+    constexpr uint32_t cb = cell_bytes(sizeof(T));
 #pragma unroll
     for (int k = 0; k < 7; ++k) {
         const int e = stream ? k - 3 : 0;
-        o.xo[k] = (uint32_t)pull_coord(x, e, nx, open_end & 1u) * (uint32_t)sizeof(T) + role_off;
-        o.yo[k] = (uint32_t)(pull_coord(y, e, ny, open_end & 2u) * nx) * (uint32_t)sizeof(T);
+        o.xo[k] = (uint32_t)pull_coord(x, e, nx, open_end & 1u) * cb + role_off;
+        o.yo[k] = (uint32_t)(pull_coord(y, e, ny, open_end & 2u) * nx) * cb;
         if constexpr (D == 3)
-            o.zo[k] = (uint32_t)(pull_coord(z, e, nz, open_end & 4u) * nxy) * (uint32_t)sizeof(T);
+            o.zo[k] = (uint32_t)(pull_coord(z, e, nz, open_end & 4u) * nxy) * cb;
         else
             o.zo[k] = 0;
     }
-    o.own = (uint32_t)x * (uint32_t)sizeof(T) + role_off;
-    o.row = (uint32_t)(y * nx + z * nxy) * (uint32_t)sizeof(T);
+    o.own = (uint32_t)x * cb + role_off;
+    o.row = (uint32_t)(y * nx + z * nxy) * cb;
 }
 
 // Energy-conserving collision (a mode beyond the paper).  With rates a_f,
@@ -453,15 +530,19 @@ __device__ __forceinline__ T energy_fix_kr(const Physics& ph, T rho,
     return ec_coef<T>(ph) * diff;
 }
 
-// Collision of one cell, one lane holding all 2Q populations (g and h).
-template <int D, class P, bool FD = false>
-__device__ __forceinline__ void collide_lane(typename P::T* g, typename P::T* h,
-                                             const Physics& ph) {
+// Collision of one cell, one lane holding all 2Q populations, reached
+// through p.get<k, i>() / p.set<k, i>() with k = 0 for g and k = 1 for h.
+// JOINT relaxes g and h in one pass over the pairs (relax_k with K = 2);
+// otherwise g, then h.
+template <int D, class P, bool FD, bool JOINT, class Acc>
+__device__ __forceinline__ void collide_lane_acc(const Acc& p, const Physics& ph) {
     using T = typename P::T;
     constexpr bool DEV = P::kDev;
     T s0, sj[3] = {0, 0, 0}, se, sh, dummy_j[3], dummy_e;
-    moment_sums<D, T>(g, s0, sj, se);
-    moment_sums<D, T>(h, sh, dummy_j, dummy_e);
+    moment_sums_of<D, T>([&](auto I) { return p.template get<0, decltype(I)::value>(); }, s0, sj,
+                         se);
+    moment_sums_of<D, T>([&](auto I) { return p.template get<1, decltype(I)::value>(); }, sh,
+                         dummy_j, dummy_e);
     T rho, drho, u[3] = {0, 0, 0}, t;
     macro<D, T, DEV>(s0, sj, se, sh, T(ph.r), ph.inv_dof, ph.half_delta, rho, drho, u, t);
     Equilibrium<D, T, DEV> eq;
@@ -475,9 +556,33 @@ __device__ __forceinline__ void collide_lane(typename P::T* g, typename P::T* h,
     const T kr = energy_fix_kr<D, T, DEV>(ph, rho, eq, want_e, se);
     const T beta_g = DEV ? drho : T(0);
     const T beta_h = DEV ? hdT * drho + hd * t + kr : T(0);
-    relax<D, T, DEV, FD>(g, eq, ph, rho, beta_g, T(ph.omega_f), drho, sj, want_e, T(1));
-    relax<D, T, DEV, FD>(h, eq, ph, hdT * rho + kr, beta_h, T(ph.omega_g),
-                         hd * (drho + rho * t) + kr, sj, T(0), T(0));
+    const RelaxPar<T> r[2] = {{rho, beta_g, T(ph.omega_f), drho, want_e, T(1)},
+                              {hdT * rho + kr, beta_h, T(ph.omega_g), hd * (drho + rho * t) + kr,
+                               T(0), T(0)}};
+    if constexpr (JOINT) {
+        relax_k<D, T, DEV, FD, 2>(p, eq, ph, r, sj);
+    } else {
+        relax_k<D, T, DEV, FD, 1>(Slice<0, Acc>{p}, eq, ph, &r[0], sj);
+        relax_k<D, T, DEV, FD, 1>(Slice<1, Acc>{p}, eq, ph, &r[1], sj);
+    }
+}
+
+// g[] and h[] arrays.
+template <typename T>
+struct LaneAcc {
+    T* g;
+    T* h;
+    template <int K, int I>
+    __device__ __forceinline__ T get() const { return K ? h[I] : g[I]; }
+    template <int K, int I>
+    __device__ __forceinline__ void set(T v) const { (K ? h : g)[I] = v; }
+};
+
+template <int D, class P, bool FD = false>
+__device__ __forceinline__ void collide_lane(typename P::T* g, typename P::T* h,
+                                             const Physics& ph) {
+    using T = typename P::T;
+    collide_lane_acc<D, P, FD, false>(LaneAcc<T>{g, h}, ph);
 }
 
 // Collision of one cell in the split layout: lane l < 32 holds the g
@@ -515,7 +620,7 @@ __device__ __forceinline__ void collide_split(typename P::T* p, int role, const 
     const T beta = DEV ? (role ? hdT * drho + hd * t + kr : drho) : T(0);
     const T want_m = role ? hd * (drho + rho * t) + kr : drho;
     relax<D, T, DEV, FD>(p, eq, ph, arho, beta, role ? T(ph.omega_g) : T(ph.omega_f), want_m, gj,
-                     want_e, role ? T(0) : T(1));
+                         want_e, role ? T(0) : T(1));
 }
 
 // Pull the lane's cell (lane layout): g and h of every population.
@@ -572,7 +677,7 @@ __device__ __forceinline__ void load_lane(const char* src, uint32_t plane,
         constexpr int kx = PULL ? v.x + 3 : 3, ky = PULL ? v.y + 3 : 3, kz = PULL ? v.z + 3 : 3;
         const char* base = src + (size_t)(2 * i) * plane + o.yo[ky] + o.zo[kz];
         g[i] = from_store<P>(load_at<S>(base, o.xo[kx]), ph, v.group);
-        h[i] = from_store<P>(load_at<S>(base + plane, o.xo[kx]), ph, v.group);
+        h[i] = from_store<P>(load_at<S>(base + h_offset(sizeof(S), plane), o.xo[kx]), ph, v.group);
     });
 }
 
@@ -583,12 +688,13 @@ __device__ __forceinline__ void store_lane(char* dst, uint32_t plane,
                                            const Physics& ph) {
     constexpr VelSet<D> V = kVelSet<D>;
     char* row = dst + o.row;
+    const uint32_t ho = h_offset(sizeof(typename P::S), plane);
     static_for<0, VelSet<D>::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int grp = V.v[i].group;
         char* base = row + (size_t)(2 * i) * plane;
         store_at(base, o.own, to_store<P>(g[i], ph, grp));
-        store_at(base + plane, o.own, to_store<P>(h[i], ph, grp));
+        store_at(base + ho, o.own, to_store<P>(h[i], ph, grp));
     });
 }
 
@@ -624,6 +730,85 @@ __device__ __forceinline__ void store_split(char* dst, uint32_t plane,
     });
 }
 
+
+// Half storage, one lane per cell.  The lane holds its cell's 107 (D3Q107) or
+// 37 (D2Q37) g/h words -- g in the low half, h in the high half -- loaded and
+// stored as whole 32-bit words, a wave's access covering 64 cells (256
+// bytes).  A value is converted where it is used, by the conversions of
+// from_store and to_store (one mixed-precision FMA with the weight), so each
+// population goes through exactly the arithmetic of the other layouts; only
+// the float is formed twice (moment sums, then relaxation) instead of being
+// kept, which keeps 214 values in 107 registers.  The relaxed value goes
+// straight back into its half of the word (v_fma_mixlo/mixhi_f16 leave the
+// other half as it is).  volatile: a conversion must not be merged with the
+// other one of the same word, which would keep the float live.
+template <bool HI>
+__device__ __forceinline__ float half_of(uint32_t w, float scale) {
+    float x;
+    if constexpr (HI)
+        asm volatile("v_fma_mix_f32 %0, %1, %2, 0 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+                     : "=v"(x) : "v"(w), "s"(scale));
+    else
+        asm volatile("v_fma_mix_f32 %0, %1, %2, 0 op_sel_hi:[1,0,0]"
+                     : "=v"(x) : "v"(w), "s"(scale));
+    return x;
+}
+
+template <bool HI>
+__device__ __forceinline__ void set_half(uint32_t& w, float v, float inv_scale) {
+    if constexpr (HI)
+        asm volatile("v_fma_mixhi_f16 %0, %1, %2, 0 op_sel_hi:[0,0,0]"
+                     : "+v"(w) : "v"(v), "s"(inv_scale));
+    else
+        asm volatile("v_fma_mixlo_f16 %0, %1, %2, 0 op_sel_hi:[0,0,0]"
+                     : "+v"(w) : "v"(v), "s"(inv_scale));
+}
+
+// g (k = 0, low half) and h (k = 1, high half) of the lane's words.
+template <int D>
+struct PairAcc {
+    uint32_t* w;
+    const Physics& ph;
+    template <int K, int I>
+    __device__ __forceinline__ float get() const {
+        return half_of<K == 1>(w[I], ph.wf[kVelSet<D>.v[I].group]);
+    }
+    template <int K, int I>
+    __device__ __forceinline__ void set(float v) const {
+        set_half<K == 1>(w[I], v, ph.inv_wf[kVelSet<D>.v[I].group]);
+    }
+};
+
+// Pull, collide and store one cell in the lane layout: F64 and F32Dev as
+// g[] and h[] arrays, half storage as g/h words.
+template <int D, class P>
+__device__ __forceinline__ void step_lane_cell(const char* src, char* dst, uint32_t plane,
+                                               const RowOffsets<typename P::S>& o,
+                                               const Physics& ph) {
+    using T = typename P::T;
+    constexpr int Q = VelSet<D>::Q;
+    if constexpr (P::kScaled) {
+        constexpr VelSet<D> V = kVelSet<D>;
+        uint32_t w[Q];
+        static_for<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            constexpr Vel v = V.v[i];
+            const char* base = src + (size_t)(2 * i) * plane + o.yo[v.y + 3] + o.zo[v.z + 3];
+            w[i] = load_at<uint32_t>(base, o.xo[v.x + 3]);
+        });
+        collide_lane_acc<D, P, false, true>(PairAcc<D>{w, ph}, ph);
+        char* row = dst + o.row;
+        static_for<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            store_at(row + (size_t)(2 * i) * plane, o.own, w[i]);
+        });
+    } else {
+        T g[Q], h[Q];
+        load_lane<D, P>(src, plane, o, g, h, ph);
+        collide_lane<D, P>(g, h, ph);
+        store_lane<D, P>(dst, plane, o, g, h, ph);
+    }
+}
 
 // ---------------------------------------------------------------------------
 // The finite-difference form (Sec. III): after the collision (which already
@@ -697,10 +882,11 @@ __device__ __forceinline__ void convect_store_lane(const char* src, char* dst, u
         constexpr int grp = V.v[i].group;
         const char* sp = src + (size_t)(2 * i) * plane;
         const T nbg = fd_neighbours<D, P, i>(sp, o, ph);
-        const T nbh = fd_neighbours<D, P, i>(sp + plane, o, ph);
+        const T nbh = fd_neighbours<D, P, i>(sp + h_offset(sizeof(typename P::S), plane), o, ph);
         char* base = row + (size_t)(2 * i) * plane;
         store_at(base, o.own, to_store<P>(g[i] - cs * nbg, ph, grp));
-        store_at(base + plane, o.own, to_store<P>(h[i] - cs * nbh, ph, grp));
+        store_at(base + h_offset(sizeof(typename P::S), plane), o.own,
+                 to_store<P>(h[i] - cs * nbh, ph, grp));
     });
 }
 

@@ -15,8 +15,10 @@ against the oracle is set by that rounding, not by the arithmetic:
     TOL_FP16_SHORT for runs of tens of steps) are a few times the errors
     measured on these seeded cases.
 
-Results are bitwise deterministic and identical between the single-solve
-path and the batched pool, alone and in a mix."""
+A cell's g and h halves share one 32-bit word in memory.  Results are
+bitwise deterministic, identical between the one-lane kernel (whole words)
+and the split kernel (one half per lane), and identical between the
+single-solve path and the batched pool, alone and in a mix."""
 import numpy as np
 import pytest
 
@@ -148,6 +150,28 @@ def test_fp16_sod_shock_tube():
         assert abs(a - b) <= 0.05 * b, (l1, l1_o)
     for y in range(1, 4):
         assert np.array_equal(g[0][y * 200:(y + 1) * 200], g[0][:200])
+
+
+ZG, PER = lbm.LBM_BC_ZERO_GRADIENT, lbm.LBM_BC_PERIODIC
+
+
+@pytest.mark.parametrize("dim,shape,bc", [
+    (3, (70, 9, 5), None),
+    (3, (45, 6, 4), lbm.LBM_BC(ZG, PER, ZG)),
+    (2, (131, 7, 1), lbm.LBM_BC(ZG, ZG)),
+])
+def test_fp16_lane_words_equal_split_bitwise(dim, shape, bc):
+    """The one-lane kernel loads and stores whole g/h words and converts each
+    half where it is used; the split kernel moves one half per lane.  Both
+    apply the same conversions and the same collision arithmetic, so their
+    states agree bit for bit (ragged rows, open and periodic ends)."""
+    f = smooth_fields(dim, *shape, seed=41)
+    kw = dict(precision=P16, bc=bc) if bc is not None else dict(precision=P16)
+    a = gpu_run(dim, 1.4, 0.7, 0.8, shape, f, 20, variant=LANE, **kw)
+    b = gpu_run(dim, 1.4, 0.7, 0.8, shape, f, 20, variant=SPLIT, **kw)
+    for x, y in zip(a[:3], b[:3]):
+        assert np.all(np.isfinite(x))
+        assert np.array_equal(x, y)
 
 
 def test_fp16_deterministic_and_conservation():
