@@ -4,7 +4,7 @@ counts, against the oracle:
   * D2Q37, periodic, the seeded 8-mode field with |k| <= 8 (seed 2), gamma
     1.4, tau_f 0.7, tau_g 0.8, 1000 steps:
       - on 512^2, every cell against the oracle run here;
-      - on the configuration's own 4096^2, at the 1030 cells of the stored
+      - on the configuration's own 4096^2, at the 1032 cells of the stored
         oracle reference (tests/golden/config2_4096.txt);
   * D3Q107, periodic, the same recipe (seed 3), tau_f = tau_g = 0.65,
     gamma 1.4 (delta 2) and 5/3 (delta 0), 500 steps, on 128 x 64 x 256, at
