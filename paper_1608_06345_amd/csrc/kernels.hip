@@ -471,13 +471,14 @@ hipError_t step_impl(bool split, const StepArgs& a0, hipStream_t s) {
     // whole rows per XCD once there are enough rows to keep all eight busy
     a.xcd_rows = a.rows >= 64 ? 1 : 0;
     const int grid = a.xcd_rows ? 8 * a.tiles_per_row * ((a.rows + 7) / 8) : (a.items + 3) / 4;
-    // Occupancy hint for the split D3Q107 kernels, at least two waves per
-    // SIMD.  Float: 4% more bandwidth than the compiler's own choice (three
-    // waves at 162 VGPRs).  Double: the compiler's choice is one wave (256
-    // VGPRs + 28 AGPRs); two waves spill 30 values to scratch and still ran
-    // 2.4% faster (10.66 against 10.92 ms at 256^3, six interleaved fresh
-    // allocations each).  The other kernels run best as compiled.
-    constexpr int kSplitWaves = D == 3 ? 2 : 1;
+    // Occupancy hint for the split D3Q107 float kernels: asking for at least
+    // two waves per SIMD gave 4% more bandwidth than the compiler's own
+    // choice (three waves at 162 VGPRs).  In double, two waves (256 VGPRs,
+    // 30 values spilled to scratch, against one wave at 256 + 28 AGPRs) ran
+    // 2.4% faster in isolated timings but not in the benchmark, and the
+    // spills added 13% to the HBM bytes; it keeps one.  The other kernels
+    // run best as compiled.
+    constexpr int kSplitWaves = (D == 3 && sizeof(typename P::T) == 4) ? 2 : 1;
     if (split)
         return launch_kernel(&k_step_split<D, P, kSplitWaves>, dim3(grid), dim3(256), s, a);
     else
