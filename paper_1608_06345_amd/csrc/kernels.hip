@@ -482,7 +482,7 @@ hipError_t step_impl(bool split, const StepArgs& a0, hipStream_t s) {
     if (split)
         return launch_kernel(&k_step_split<D, P, kSplitWaves>, dim3(grid), dim3(256), s, a);
     else
-        return launch_kernel(&k_step<D, P, P::kScaled ? 3 : 1>, dim3(grid), dim3(256), s, a);
+        return launch_kernel(&k_step<D, P, 1>, dim3(grid), dim3(256), s, a);
 }
 
 template <int D, class P>
