@@ -2,8 +2,10 @@
 // the fused finite-difference step (Sec. III; its two-pass form is in
 // fd.hip), and the FP64 readout / conservation reductions.
 //
-// Data layout in HBM (one ping-pong side): [Q][2][P] -- for population i the
-// g plane (N values, x fastest, in a slot of P >= N) and then the h plane.  Every plane is read
+// Data layout in HBM (one ping-pong side): population i owns a slab of 2 P
+// values (P >= N, x fastest).  FP64 and FP32: the g plane, then the h plane
+// ([Q][2][P]); half storage: the g and h halves of a cell side by side in
+// one 32-bit word ([Q][P][2]; cell_bytes, h_offset).  Every value is read
 // once and written once per step: one HBM read and one HBM write per
 // population per cell.
 //

@@ -48,7 +48,7 @@ struct Physics {
 // Arguments of the fused step kernel (passed by value in the kernarg
 // segment, so every field is wave-uniform and lives in SGPRs).
 struct StepArgs {
-    const void* src;      // [Q][2][P]: per population the g plane, then the h plane
+    const void* src;      // one ping-pong side (layout: cell_bytes, h_offset)
     void* dst;            // same layout
     int64_t N;            // cells
     int64_t P;            // plane stride in cells (>= N; see plane_stride)

@@ -5,7 +5,7 @@
 // Device state
 //   arena      one allocation; each resident solve owns a contiguous region
 //              of two ping-pong sides laid out exactly as a single solve's
-//              ([Q][2][N] per side).
+//              (see cell_bytes, h_offset).
 //   table      static per-slot parameters (geometry, physics, step budget),
 //              written by the host when membership changes.
 //   steps_done per-slot step counters, advanced on the device by k_advance

@@ -33,11 +33,11 @@ __device__ __forceinline__ void store_at(char* base, uint32_t byte_off, T v) {
     __builtin_nontemporal_store(v, reinterpret_cast<T*>(base + byte_off));
 }
 
-// Ordinary (cached) store.  A split-layout wave writes 32 cells of a plane;
-// in half storage that is 64 bytes, half a 128-byte line, and the other half
-// comes from the neighbouring wave.  Through the cache the halves meet in L2
-// before the line goes out (measured 4-5% faster at D3Q107 256^3 than
-// streaming them; in the lane layout, whole lines, streaming stays faster).
+// Ordinary (cached) store, for the split layout in half storage: its lanes
+// write single halves into the g/h words (g lanes the low, h lanes the high
+// halves of one line).  Through the cache or streamed measured the same
+// (6.2 ms per D3Q107 256^3 step); the one-lane kernel, which AUTO takes in
+// half storage, stores whole words.
 template <typename T>
 __device__ __forceinline__ void store_cached(char* base, uint32_t byte_off, T v) {
     *reinterpret_cast<T*>(base + byte_off) = v;
