@@ -162,7 +162,8 @@ int lbm_destroy(lbm_handle h);
  * its own.  The stream is borrowed, not owned: it must outlive its use. */
 int lbm_set_stream(lbm_handle h, void *stream);
 /* Kernel layout of the step (a tuning choice; results agree to round-off).
- *   LANE      fused kernel, one lane holds all 2Q populations of a cell;
+ *   LANE      fused kernel, one lane holds all 2Q populations of a cell
+ *             (half storage: as 2Q halves in Q g/h words);
  *   SPLIT     fused kernel, a lane pair holds them, g in lane l and h in
  *             lane l + 32 of the wave;
  *   TWO_PASS  (lbm_create_fd solves only) the finite-difference step as a
@@ -175,9 +176,10 @@ int lbm_set_stream(lbm_handle h, void *stream);
  *             population's shifted row once, four cells a lane, and each
  *             lane reads its pulled value from LDS (same results to
  *             rounding);
- *   AUTO      (the default) lattice streaming: LANE for D2Q37, SPLIT for
- *             D3Q107, whose 214 populations do not fit one lane's
- *             registers; finite differences: TWO_PASS, except LANE for
+ *   AUTO      (the default) lattice streaming: LANE for D2Q37 and for half
+ *             storage, SPLIT for D3Q107 in FP64 and FP32, whose 214
+ *             populations do not fit one lane's registers; finite
+ *             differences: TWO_PASS, except LANE for
  *             D2Q37 in FP64 when nx is not a multiple of 256, where the
  *             fused kernel is faster than the two-pass step without LDS.
  * EINVAL for other values, for TWO_PASS on a lattice-streaming solve, and for
