@@ -150,8 +150,9 @@ __device__ __forceinline__ T fmadd(T a, T b, T c) {
 // a multiply w * (...) fused into a later sum would let that sum see the
 // unrounded target, and the correction would then not cancel the rounding
 // of the targets it is applied to (measured: 10x the float32 error on a
-// shock tube).
-// Even and odd parts of P(c): P(+-c) = even +- odd.
+// shock tube).  pair_parts forms the even and odd parts of P(c), P(+-c) =
+// even +- odd, which do not depend on the distribution; pair_finish the two
+// targets of one distribution from them.
 template <typename T>
 __device__ __forceinline__ void pair_parts(T A0, T A1, T A2, T c, T& even, T& odd) {
 #pragma clang fp contract(off)
@@ -309,17 +310,18 @@ __device__ __forceinline__ float fd_scale<float>(const Physics& ph) { return ph.
 // population also loses the centre term of its upwind-biased convection,
 // 3 |e_i|_1 (dt r / 6) p_i, taken from the pre-collision value; the
 // neighbour terms are added by convect_store_* below.
-// Relaxation parameters of one distribution (see relax).
+//
+// relax_k does this for K distributions of one cell at once (K = 2: g and h
+// of a lane that holds both): each pair's polynomial is formed once and
+// serves every distribution.  Per distribution the arithmetic, and the order
+// of every sum, is that of K = 1.  p.get<k, i>() / p.set<k, i>(v):
+// population i of distribution k; r[k]: its parameters; relax: one
+// distribution held in an array.
 template <typename T>
 struct RelaxPar {
     T arho, beta, omega, want_m, want_e, je_on;
 };
 
-// relax for K distributions of one cell at once (K = 2: g and h of a lane
-// that holds both): each pair's polynomial is formed once and serves every
-// distribution.  Per distribution the arithmetic, and the order of every
-// sum, is that of K = 1.  p.get<k, i>() / p.set<k, i>(v): population i of
-// distribution k.
 template <int D, typename T, bool DEV, bool FD, int K, class Acc>
 __device__ __forceinline__ void relax_k(const Acc& p, const Equilibrium<D, T, DEV>& eq,
                                         const Physics& a, const RelaxPar<T>* r,
