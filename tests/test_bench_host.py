@@ -36,6 +36,25 @@ def test_headline_and_paths():
     assert len(bench.kernel_source_hash()) == 16
 
 
+def test_kernel_hash_follows_code_not_comments():
+    code = "int a = 1; // one\n/* block\n comment */\nint b = a / 2;  \n\n"
+    assert bench._code_only(code) == "int a = 1;\nint b = a / 2;"
+    assert bench._code_only("x /* a */ + /* b */ y") == "x  +  y"
+    # a changed comment leaves the code the same, a changed operator does not
+    assert bench._code_only(code.replace("one", "two")) == bench._code_only(code)
+    assert bench._code_only(code.replace("a / 2", "a * 2")) != bench._code_only(code)
+    # the traffic record is used only for the hash of the current sources
+    import json
+    with open(os.path.join(bench.ROOT, "profiles", "traffic.json")) as fh:
+        rec = json.load(fh)
+    hashes = {v["kernel_hash"] for v in rec.values() if isinstance(v, dict)}
+    assert hashes, "no traffic entries"
+    for name, ent in rec.items():
+        if isinstance(ent, dict):
+            want = ent["bytes_per_launch"] if ent["kernel_hash"] == bench.kernel_source_hash() else None
+            assert bench.measured_traffic(name, ent["cells"]) == want
+
+
 def test_gamma_five_thirds_path_keeps_h():
     p = bench.PATHS["d3q107_fp32_gamma53"]
     assert abs(p["gamma"] - 5.0 / 3.0) < 1e-15 and p["store"] == "fp32"
