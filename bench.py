@@ -313,7 +313,7 @@ def serving_runs(n_requests, servers=("pool", "sequential"), ensemble=True, rate
                           "calibration_requests": 48, "makespan_s": cal_sum["makespan_s"]}
         torch.cuda.empty_cache()
         print(f"# serving capacity on the mix: {pt['capacity']}", file=sys.stderr, flush=True)
-    every = 50 if n_requests >= 200 else 0
+    every = 50 if n_requests >= 200 else (25 if n_requests >= 48 else 0)
     pt["rate_per_s"] = round(rate, 3)
     if "pool" in servers:
         trace = serving.poisson_trace(n_requests, rate, seed=5)
@@ -540,7 +540,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the batched tube ensemble and the serving trace")
-    ap.add_argument("--serving-requests", type=int, default=24,
+    ap.add_argument("--serving-requests", type=int, default=96,
                     help="requests in the Poisson serving trace")
     ap.add_argument("--serving-only", choices=("pool", "sequential", "both"), default=None,
                     help="after the headline path, run only the Poisson serving trace with "
