@@ -203,6 +203,11 @@ def test_fp16_pool_alone_mix_and_single_solve():
         (lbm.make_request(2, 1.25, 0.8, 0.8, 300, 4, bc=OPEN_X, steps=40),
          sod_fields(2, 300, 4, left=(1.0, 0.0, 1.2), right=(0.6, 0.0, 0.6))),
         (lbm.make_request(2, 2.0, 0.6, 0.6, 128, 66, steps=31), shear_wave_fields(2, 128, 66, seed=35)),
+        # D3Q107 g/h words, one lane per cell, with a ragged row and open x and z ends
+        (lbm.make_request(3, 1.4, 0.7, 0.75, 70, 6, 5, bc=lbm.LBM_BC(lbm.LBM_BC_ZERO_GRADIENT,
+                                                                    lbm.LBM_BC_PERIODIC,
+                                                                    lbm.LBM_BC_ZERO_GRADIENT),
+                          steps=19), smooth_fields(3, 70, 6, 5, seed=36)),
     ]
 
     def run_to_end(pool, slots):
